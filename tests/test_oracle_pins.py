@@ -1,0 +1,423 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each checks a moment identity of the
+paper's appendix, a closed form, a conservation law, an analytic flow, a symmetry, or an
+independent brute-force reading of the step in 40-digit arithmetic.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import diag
+from paper_1710_09541_amd import cases
+
+CS2 = 1.0 / 3.0
+RNG = np.random.default_rng(12345)
+
+
+def _lat():
+    cx, cy, w, opp = O.lattice()
+    return cx.astype(float), cy.astype(float), w, opp
+
+
+# ------------------------------------------------------------------ lattice (Eq. 10)
+
+def test_lattice_isotropy():
+    cx, cy, w, opp = _lat()
+    assert np.isclose(w.sum(), 1.0, rtol=0, atol=1e-15)
+    c = np.stack([cx, cy])
+    assert np.allclose(c @ w, 0.0, atol=1e-16)
+    # second moment c_s^2 delta, fourth moment c_s^4 (dd + dd + dd)
+    m2 = np.einsum("i,ai,bi->ab", w, c, c)
+    assert np.allclose(m2, CS2 * np.eye(2), atol=1e-15)
+    m4 = np.einsum("i,ai,bi,ci,di->abcd", w, c, c, c, c)
+    d = np.eye(2)
+    delta4 = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+              + np.einsum("ad,bc->abcd", d, d))
+    assert np.allclose(m4, CS2 * CS2 * delta4, atol=1e-15)
+    # opposite directions, speeds 0, 1 and sqrt 2, and the angles of Eq. 10
+    assert np.all(cx[opp] == -cx) and np.all(cy[opp] == -cy)
+    for i in range(1, 5):
+        a = (i - 1) * np.pi / 2
+        assert np.isclose(cx[i], np.cos(a), atol=1e-12) and np.isclose(cy[i], np.sin(a), atol=1e-12)
+    for i in range(5, 9):
+        a = (i - 5) * np.pi / 2 + np.pi / 4
+        assert np.isclose(cx[i], np.sqrt(2) * np.cos(a), atol=1e-12)
+        assert np.isclose(cy[i], np.sqrt(2) * np.sin(a), atol=1e-12)
+
+
+# ------------------------------------------------------ moment identities (P1, App. A)
+
+@pytest.mark.parametrize("trial", range(5))
+def test_feq_moments(trial):
+    cx, cy, w, _ = _lat()
+    phi, ux, uy = RNG.uniform(-0.2, 1.2), RNG.uniform(-0.1, 0.1), RNG.uniform(-0.1, 0.1)
+    fe = O.feq(phi, ux, uy)
+    assert abs(fe.sum() - phi) < 1e-15
+    assert abs(cx @ fe - phi * ux) < 1e-16 and abs(cy @ fe - phi * uy) < 1e-16
+    # second moment phi c_s^2 I (what makes the diffusive flux M grad phi)
+    assert abs((cx * cx) @ fe - phi * CS2) < 1e-15 and abs((cx * cy) @ fe) < 1e-16
+
+
+@pytest.mark.parametrize("trial", range(5))
+def test_geq_moments_A1(trial):
+    cx, cy, w, _ = _lat()
+    p, rho = RNG.uniform(-1e-2, 1e-2), RNG.uniform(1.0, 1000.0)
+    u = RNG.uniform(-0.05, 0.05, size=2)
+    ge = O.geq(p, rho, u[0], u[1])
+    c = np.stack([cx, cy])
+    tol = 1e-13 * rho
+    assert abs(ge.sum()) < tol                                  # sum g^eq = 0
+    assert np.allclose(c @ ge, rho * u, atol=tol)               # = rho u
+    m2 = np.einsum("ai,bi,i->ab", c, c, ge)
+    assert np.allclose(m2, rho * np.outer(u, u) + p * np.eye(2), atol=tol)
+    m3 = np.einsum("ai,bi,gi,i->abg", c, c, c, ge)
+    d = np.eye(2)
+    delta = (np.einsum("ab,gt->abgt", d, d) + np.einsum("ag,bt->abgt", d, d)
+             + np.einsum("at,bg->abgt", d, d))
+    assert np.allclose(m3, rho * CS2 * np.einsum("abgt,t->abg", delta, u), atol=tol)
+
+
+@pytest.mark.parametrize("trial", range(5))
+def test_fsource_moments(trial):
+    cx, cy, w, _ = _lat()
+    tau = RNG.uniform(0.55, 2.0)
+    D = RNG.uniform(-1e-3, 1e-3, size=2)
+    lam = RNG.uniform(0, 0.25)
+    ang = RNG.uniform(0, 2 * np.pi)
+    n = np.array([np.cos(ang), np.sin(ang)])
+    fs = O.fsource(tau, D[0], D[1], lam, n[0], n[1])
+    k = 1.0 - 1.0 / (2.0 * tau)
+    assert abs(fs.sum()) < 1e-17                                # mass is not created
+    # first moment (1 - 1/(2 tau)) [d_t(phi u) + c_s^2 lambda n]  (Eq. 11)
+    assert np.allclose([cx @ fs, cy @ fs], k * (D + CS2 * lam * n), atol=1e-16)
+
+
+@pytest.mark.parametrize("trial", range(5))
+def test_gforce_moments_A2(trial):
+    cx, cy, w, _ = _lat()
+    tau = RNG.uniform(0.51, 3.0)
+    F = RNG.uniform(-1e-4, 1e-4, size=2)
+    u = RNG.uniform(-0.05, 0.05, size=2)
+    gphi = RNG.uniform(-0.2, 0.2, size=2)
+    drho = RNG.uniform(1.0, 999.0)
+    G = O.gforce(tau, F[0], F[1], drho, u[0], u[1], gphi[0], gphi[1])
+    k = 1.0 - 1.0 / (2.0 * tau)
+    grho = drho * gphi                                           # Eq. 13 gradient
+    c = np.stack([cx, cy])
+    tol = 1e-14 * drho
+    assert abs(G.sum() - k * u @ grho) < tol
+    assert np.allclose(c @ G, k * F, atol=tol)
+    lam = np.einsum("ai,bi,i->ab", c, c, G)
+    expect = k * CS2 * (np.outer(u, grho) + np.outer(grho, u) + (u @ grho) * np.eye(2))
+    assert np.allclose(lam, expect, atol=tol)
+
+
+def test_eq18_equals_eq20():
+    """Eq. 18 (general form with grad rho) and Eq. 20 (after Eqs. 5 and 13) agree."""
+    cx, cy, w, _ = _lat()
+    for _ in range(5):
+        tau = RNG.uniform(0.51, 3.0)
+        mu_phi = RNG.uniform(-1e-3, 1e-3)
+        gphi = RNG.uniform(-0.2, 0.2, size=2)
+        Gb = RNG.uniform(-1e-5, 1e-5, size=2)
+        u = RNG.uniform(-0.05, 0.05, size=2)
+        drho = RNG.uniform(1.0, 999.0)
+        F = mu_phi * gphi + Gb
+        grho = drho * gphi
+        eq18 = np.empty(9)
+        for i in range(9):
+            c = np.array([cx[i], cy[i]])
+            cc = np.outer(c, c) - CS2 * np.eye(2)
+            eq18[i] = (1 - 1 / (2 * tau)) * w[i] * (u @ grho + c @ F / CS2
+                                                   + np.sum(np.outer(u, grho) * cc) / CS2)
+        eq20 = O.gforce(tau, F[0], F[1], drho, u[0], u[1], gphi[0], gphi[1])
+        assert np.allclose(eq18, eq20, rtol=0, atol=1e-15 * drho)
+
+
+def test_moments_invert_equilibrium():
+    """With a uniform phi (no gradient) and no body force, Eq. 22 applied to
+    g = g^eq(p, u) gives back u and p (P3); a body force G shifts u by G / (2 rho)."""
+    case = cases.static_drop(8, 8)
+    for _ in range(5):
+        phi = RNG.uniform(0, 1)
+        rho = phi * (case["rho_l"] - case["rho_g"]) + case["rho_g"]
+        p, u = RNG.uniform(-1e-2, 1e-2), RNG.uniform(-0.05, 0.05, size=2)
+        g = O.geq(p, rho, u[0], u[1])
+        case["sigma"] = 0.0
+        out = O.closure(case, phi, 0.0, 0.0, 0.0, g)
+        assert abs(out["rho"] - rho) < 1e-12
+        assert np.allclose([out["u_x"], out["u_y"]], u, rtol=0, atol=1e-15)
+        assert abs(out["p"] - p) < 1e-13 * rho
+        case["Gx"], case["Gy"] = 1e-5, -3e-6
+        out = O.closure(case, phi, 0.0, 0.0, 0.0, g)
+        assert np.allclose([out["u_x"], out["u_y"]], u + 0.5 * np.array([1e-5, -3e-6]) / rho,
+                           rtol=0, atol=1e-15)
+        case["Gx"], case["Gy"] = 0.0, 0.0
+
+
+def test_closure_constants():
+    """k = 1.5 sigma W and beta = 12 sigma / W (Eq. 7) enter mu_phi (Eq. 6); lambda (Eq. 3);
+    tau_g from nu (Eq. 23) for each viscosity law (Eqs. 24-26)."""
+    case = cases.static_drop(8, 8, W=4.0, sigma=0.01, ratio=100.0, nu=0.1)
+    case.update(nu_l=0.1, nu_g=0.4)
+    g = np.zeros(9)
+    phi, lap = 0.3, 0.02
+    k, beta = 1.5 * 0.01 * 4.0, 12 * 0.01 / 4.0
+    out = O.closure(case, phi, 0.0, 0.0, lap, g)
+    assert np.isclose(out["mu_phi"], 4 * beta * phi * (phi - 1) * (phi - 0.5) - k * lap, rtol=1e-14)
+    assert np.isclose(out["lambda"], 4 * phi * (1 - phi) / 4.0, rtol=1e-14)
+    rho = phi * 99 + 1
+    for law, nu in ((cases.NU_LINEAR, phi * (0.1 - 0.4) + 0.4),
+                    (cases.NU_INVERSE, 1 / (phi * (1 / 0.1 - 1 / 0.4) + 1 / 0.4)),
+                    (cases.MU_STEP, 1.0 * 0.4 / rho)):
+        case["visc_law"] = law
+        assert np.isclose(O.closure(case, phi, 0.0, 0.0, lap, g)["tau_g"], 3 * nu + 0.5, rtol=1e-14)
+    case["visc_law"] = cases.MU_STEP      # the tie phi = 0.5 goes to the liquid
+    assert np.isclose(O.closure(case, 0.5, 0, 0, 0, g)["tau_g"], 3 * 100 * 0.1 / 50.5 + 0.5)
+
+
+# ------------------------------------------------------------- stencils (P4, Eqs. 27-28)
+
+def test_stencil_fourier_modes():
+    n = 32
+    case = cases.static_drop(n, n)
+    x = np.arange(n)
+    X, Y = np.meshgrid(x, x)
+    for m in (1, 3, 5):
+        k = 2 * np.pi * m / n
+        gx, gy, lap = O.stencil(case, np.sin(k * X))
+        assert np.allclose(gx, np.sin(k) * np.cos(k * X), atol=1e-14)
+        assert np.allclose(gy, 0.0, atol=1e-14)
+        assert np.allclose(lap, -4 * np.sin(k / 2) ** 2 * np.sin(k * X), atol=1e-14)
+        # diagonal mode: the same 1D symbols along x and y
+        gx, gy, lap = O.stencil(case, np.sin(k * (X + Y)))
+        s = np.sin(k * (X + Y))
+        c = np.cos(k * (X + Y))
+        sym_g = np.sin(k) * (2.0 / 3.0 + np.cos(k) / 3.0)
+        assert np.allclose(gx, sym_g * c, atol=1e-14) and np.allclose(gy, sym_g * c, atol=1e-14)
+        sym_l = 6 * (4 / 9 * (np.cos(k) - 1) + 1 / 36 * (2 * np.cos(2 * k) - 2))
+        assert np.allclose(lap, sym_l * s, atol=1e-13)
+
+
+def test_stencil_polynomials_and_mirror_rows():
+    """Exact for polynomials of degree <= 2 away from the edges; next to a wall the ghost row
+    mirrors the first row, so the normal derivative of a field constant in x is one-sided."""
+    case = cases.layered_poiseuille(16, 16)
+    y = np.arange(16) + 0.5
+    X, Y = np.meshgrid(np.arange(16) + 0.5, y)
+    gx, gy, lap = O.stencil(case, 2.0 + 0.3 * Y + 0.01 * Y * Y)
+    assert np.allclose(gy[1:-1], 0.3 + 0.02 * Y[1:-1], atol=1e-13)
+    assert np.allclose(lap[1:-1], 0.02, atol=1e-13)
+    assert np.allclose(gx, 0.0, atol=1e-13)
+    v = 2.0 + 0.3 * Y + 0.01 * Y * Y
+    assert np.allclose(gy[0], (v[1] - v[0]) / 2.0, atol=1e-13)
+    assert np.allclose(gy[-1], (v[-1] - v[-2]) / 2.0, atol=1e-13)
+    assert np.allclose(lap[0], v[1] - v[0], atol=1e-13)
+
+
+def test_mu_phi_planar_residual_falls_as_W2():
+    """The continuum tanh profile makes mu_phi vanish (Eqs. 6-7); the discrete residual
+    falls like W^-2 (P5)."""
+    res = []
+    for W in (4.0, 8.0, 16.0):
+        case = cases.planar_interface(nx=4, ny=512, W=W, sigma=0.01)
+        gx, gy, lap = O.stencil(case, case["phi0"])
+        col = [O.closure(case, case["phi0"][j, 0], gx[j, 0], gy[j, 0], lap[j, 0], np.zeros(9))
+               for j in range(512)]
+        mu = np.array([c["mu_phi"] for c in col])
+        beta = 12 * 0.01 / W
+        res.append(np.max(np.abs(mu)) / beta)
+    assert res[0] < 0.02
+    assert 3.7 < res[1] / res[2] < 4.3
+
+
+# ------------------------------------------------------------- conservation (P6)
+
+@pytest.mark.parametrize("make", [lambda: cases.static_drop(32, 32, R=8),
+                                  lambda: cases.layered_poiseuille(8, 48),
+                                  lambda: cases.droplet_impact(64, 48, D=20, Re=20)])
+def test_sum_phi_conserved(make):
+    c = make()
+    s = O.OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
+    m0 = s.moments()["phi"].sum()
+    s.step(600)
+    m1 = s.moments()["phi"].sum()
+    if c["bc_yhi"] == cases.OPEN:
+        # mass can leave through the open top; it stays essentially all in the domain here
+        assert abs(m1 - m0) / m0 < 1e-6
+    else:
+        # exact in exact arithmetic (sum_i f_i^eq = phi, sum_i F_i = 0); in FP64 the drift
+        # is bounded by a small multiple of the unit round-off per step
+        assert abs(m1 - m0) / m0 < 20 * np.finfo(float).eps * 600
+
+
+# -------------------------------------------------------- physics (P7, P8, P9, P10, P14)
+
+def _dp(case, warm, samples=20, every=50):
+    s = O.OracleSim(case, case["phi0"], case["ux0"], case["uy0"])
+    s.step(warm)
+    v = []
+    for _ in range(samples):
+        s.step(every)
+        d = diag.diagnostics(s.moments(), case["rho_l"], case["rho_g"], case["mask"])
+        v.append(d["p_in"] - d["p_out"])
+    return float(np.mean(v)), s
+
+
+def test_laplace_law():
+    """Young-Laplace in 2D: the pressure jump of a static drop is sigma / R.  The error of
+    the diffuse interface falls with W (W = 4 within 10 %, W = 6 closer)."""
+    ratios = {}
+    for R in (12.0, 20.0):
+        c = cases.static_drop(64, 64, R=R, W=4.0, sigma=0.01)
+        dp, _ = _dp(c, 3000)
+        ratios[R] = dp * R / 0.01
+    for r in ratios.values():
+        assert 0.9 < r < 1.05
+    c = cases.static_drop(96, 96, R=24.0, W=6.0, sigma=0.01)
+    dp6, _ = _dp(c, 5000)
+    assert abs(dp6 * 24.0 / 0.01 - 1) < 0.6 * abs(ratios[20.0] - 1)
+
+
+def test_static_drop_rest_and_centre_line_density():
+    """Sec. 3.1: the drop stays at rest (spurious currents tiny against the capillary speed
+    sigma / (rho_l nu_l)); the density on the centre line follows rho(phi_tanh) (Eq. 13 on
+    Eq. 30) and the drop keeps its mirror and transpose symmetries to round-off."""
+    c = cases.static_drop()
+    s = O.OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
+    s.step(2000)
+    m = s.moments()
+    assert np.sqrt(m["ux"] ** 2 + m["uy"] ** 2).max() < 1e-2 * c["u_scale"]
+    rho0 = c["phi0"] * (c["rho_l"] - c["rho_g"]) + c["rho_g"]
+    assert np.max(np.abs(m["rho"][32] - rho0[32])) < 2e-2 * c["rho_l"]
+    phi = m["phi"]
+    assert np.max(np.abs(phi - phi[:, ::-1])) < 1e-12
+    assert np.max(np.abs(phi - phi[::-1, :])) < 1e-12
+    assert np.max(np.abs(phi - phi.T)) < 1e-12
+
+
+def test_layered_poiseuille_ratio10_table1():
+    """Sec. 3.2 at the paper's own set-up (100 x 10 channel, u_c = 1e-4, W = 5,
+    sigma = 1e-3, nu_l = 0.1, M = 0.1, step mu): steady E_u (Eq. 32) for density ratio 10
+    within 3x of the paper's 8.9e-3, and the profile has the analytic shape (Eq. 31)."""
+    c = cases.layered_poiseuille(nx=4, ny=100, ratio=10.0, nu_l=0.1, nu_g=0.1, u_c=1e-4,
+                                 init="analytic")
+    s = O.OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
+    s.step(20000)
+    eu = cases.relative_error_eu(s.moments()["ux"], c["ux_analytic"])
+    assert eu < 3 * 8.9e-3
+
+
+def test_layered_poiseuille_single_phase_second_order():
+    """Equal densities and viscosities: the channel holds a single fluid and the steady
+    profile is the parabola of Eq. 31 with mu_l = mu_g; the BGK scheme with half-way
+    bounce-back walls converges to it at second order in the grid spacing."""
+    eu = []
+    for ny, steps in ((16, 4000), (32, 8000)):
+        c = cases.layered_poiseuille(nx=4, ny=ny, ratio=1.0, nu_l=0.1, nu_g=0.1, u_c=1e-4,
+                                     init="analytic", sigma=0.0)
+        s = O.OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
+        s.step(steps)
+        eu.append(cases.relative_error_eu(s.moments()["ux"], c["ux_analytic"]))
+    assert eu[1] < 1e-3
+    assert 3.8 < eu[0] / eu[1] < 4.2
+
+
+def test_taylor_green_decay():
+    """Single phase (rho_l = rho_g, sigma = 0): the vortex decays as exp(-2 nu k^2 t) with
+    nu = c_s^2 (tau_g - 1/2) (Eq. 23); the measured viscosity converges at second order."""
+    err = []
+    for n in (16, 32):
+        c = cases.taylor_green(n=n, nu=0.05, u0=1e-4)
+        s = O.OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
+        s.step(10)                       # let the non-equilibrium part settle
+        a0 = np.abs(s.moments()["ux"]).max()
+        T = 100 * (n // 16) ** 2
+        s.step(T)
+        a1 = np.abs(s.moments()["ux"]).max()
+        nu_eff = -np.log(a1 / a0) / (2 * c["k"] ** 2 * T)
+        err.append(abs(nu_eff / 0.05 - 1))
+    assert err[1] < 1e-3
+    assert 3.0 < err[0] / err[1] < 4.5
+
+
+def test_galilean_translation():
+    """A flat interface carried by a uniform flow across a periodic box returns to its
+    starting profile (single phase, sigma = 0; the d_t(phi u) term of Eq. 11 keeps the
+    recovered equation Galilean invariant)."""
+    c = cases.planar_interface(nx=4, ny=64, W=4.0, ratio=1.0, sigma=0.0, uy=0.02)
+    s = O.OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
+    s.step(3200)     # 64 / 0.02 steps: once round the box
+    phi = s.moments()["phi"]
+    assert np.max(np.abs(phi - c["phi0"])) < 0.02
+
+
+# ---------------------------------------------------- brute force (P11, step order)
+
+@pytest.mark.parametrize("bc", [(cases.PERIODIC, cases.PERIODIC), (cases.WALL, cases.WALL),
+                                (cases.WALL, cases.OPEN), (cases.OPEN, cases.WALL)])
+@pytest.mark.parametrize("law", [cases.NU_LINEAR, cases.MU_STEP])
+def test_bruteforce_4x4(bc, law):
+    import mpmath as mp
+
+    from tests import bruteforce_mp as B
+    c = cases.random_state_case(4, 4, seed=3 + law)
+    c["bc_ylo"], c["bc_yhi"] = bc
+    c["visc_law"] = law
+    s = O.OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
+    rng = np.random.default_rng(7)
+    f = rng.uniform(0.02, 0.1, size=(9, 4, 4))
+    g = rng.uniform(-1e-3, 1e-3, size=(9, 4, 4))
+    q = rng.uniform(-1e-3, 1e-3, size=(2, 4, 4))
+    s.set_state(f, g, q)
+    prm = B.to_mp({k: c[k] for k in cases.PARAM_KEYS + ("visc_law",)})
+    grid = B.Grid(4, 4, *bc)
+    F = [[[mp.mpf(float(f[i, y, x])) for i in range(9)] for x in range(4)] for y in range(4)]
+    G = [[[mp.mpf(float(g[i, y, x])) for i in range(9)] for x in range(4)] for y in range(4)]
+    Q = [[(mp.mpf(float(q[0, y, x])), mp.mpf(float(q[1, y, x]))) for x in range(4)]
+         for y in range(4)]
+    for _ in range(3):
+        F, G, Q = B.step(prm, grid, F, G, Q)
+        s.step(1)
+    fo, go, qo = s.get_state()
+    mb = B.moments(prm, grid, F, G, Q)
+    mo = s.moments()
+    for y in range(4):
+        for x in range(4):
+            for i in range(9):
+                assert abs(float(F[y][x][i]) - fo[i, y, x]) < 1e-15
+                assert abs(float(G[y][x][i]) - go[i, y, x]) < 1e-15
+            assert abs(float(Q[y][x][0]) - qo[0, y, x]) < 1e-16
+            for key in ("phi", "rho", "p", "ux", "uy"):
+                ref = float(mb[y][x][key])
+                assert abs(ref - mo[key][y, x]) <= 1e-13 * max(1.0, abs(ref))
+
+
+# ------------------------------------------------------------- parameters and diagnostics
+
+def test_parameter_validation():
+    good = cases.static_drop(8, 8)
+    assert O.check(good) == 0
+    for k, v in (("nx", 2), ("rho_g", 0.0), ("W", -1.0), ("M", 0.0), ("visc_law", 7)):
+        bad = dict(good)
+        bad[k] = v
+        assert O.check(bad) != 0
+    bad = dict(good)
+    bad["bc_ylo"] = cases.WALL          # periodic on one side only
+    assert O.check(bad) != 0
+
+
+def test_diag_definitions():
+    ny, nx = 8, 16
+    phi = np.zeros((ny, nx))
+    phi[:, 4:10] = 1.0                  # a vertical liquid stripe: two crossings per row
+    m = dict(phi=phi, rho=1 + 9 * phi, p=np.where(phi > 0.5, 2.0, 1.0), ux=np.zeros_like(phi),
+             uy=np.full_like(phi, 0.1))
+    d = diag.diagnostics(m, 10.0, 1.0, mask=(7.0, 4.0, 2.5, 7.5, 3.0))
+    assert d["interface_crossings"] == 2 * ny
+    assert np.isclose(d["sum_phi"], 6 * ny)
+    assert np.isclose(d["kinetic"], 0.5 * 0.01 * np.sum(1 + 9 * phi))
+    assert d["p_in"] == 2.0 and d["p_out"] == 1.0
+    assert np.isclose(d["spread_radius"], 3.0)
+    assert d["nonfinite"] == 0
