@@ -1,0 +1,164 @@
+/*
+ * lbm.h -- C-ABI of the MI355X (gfx950) phase-field lattice Boltzmann library.
+ *
+ * The library advances the two coupled D2Q9 lattices of Liang et al., "Phase-field-based
+ * lattice Boltzmann modeling of large-density-ratio two-phase flows" (arXiv:1710.09541):
+ *   f_i  conservative Allen-Cahn equation for the order parameter phi  (Sec. 2.2, Eqs. 8-14)
+ *   g_i  incompressible Navier-Stokes with the forcing distribution G_i (Sec. 2.3, Eqs. 15-28)
+ * on one GPU, for one or many independent instances ("batch") at once.
+ *
+ * Problem statement (Sec. 2.1 and the set-ups of Sec. 3): a 2D nx x ny lattice with
+ * dx = dt = 1, x always periodic, each y side periodic, a half-way bounce-back wall or an
+ * open (zero-gradient) side; phase densities rho_l, rho_g, viscosities nu_l, nu_g with a
+ * viscosity law (Eqs. 24-26), surface tension sigma, interface width W, mobility M, a
+ * uniform body-force density G = (Gx, Gy); initial phi(x, y) and u(x, y).
+ *
+ * Conventions
+ *   - Fields on the host are double, row-major [ny][nx] (x fastest).  Node (i, j) sits at the
+ *     cell centre (i + 0.5, j + 0.5); a wall lies on the domain edge y = 0 or y = ny.
+ *   - All calls return LBM_OK (0) or a negative LBM_ERR_* code; lbm_last_error() gives the
+ *     message.  Parameters are validated before any device call, so a bad parameter set is
+ *     reported as LBM_ERR_PARAM even on a machine without a GPU.
+ *   - Kernel faults surface at the next synchronising call as LBM_ERR_DEVICE.
+ *   - lbm_step is stream-ordered and returns before the work completes; lbm_moments,
+ *     lbm_reduce and the state calls synchronise the library's stream.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx; /* opaque; owned by the library until lbm_destroy */
+
+enum {
+    LBM_OK = 0,
+    LBM_ERR_PARAM = -1,     /* invalid parameter or argument */
+    LBM_ERR_ALLOC = -2,     /* host or device allocation failed */
+    LBM_ERR_DEVICE = -3,    /* HIP runtime error (no device, launch failure, fault) */
+    LBM_ERR_NONFINITE = -4, /* a non-finite value was found by a periodic check */
+    LBM_ERR_RANGE = -5      /* index or size out of range */
+};
+
+/* y boundary of one side (x is always periodic) */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1, LBM_BC_OPEN = 2 };
+
+/* viscosity law: Eq. 24 nu linear in phi; Eq. 25 1/nu linear in phi; Eq. 26 step in the
+ * dynamic viscosity (mu_l for phi >= 0.5, else mu_g) with nu = mu / rho(phi) */
+enum { LBM_VISC_LINEAR = 0, LBM_VISC_INVERSE = 1, LBM_VISC_STEP_MU = 2 };
+
+/* storage of the distributions.  F64: doubles, FP64 arithmetic.  F32 / F16: the stored
+ * value is (f_i - w_i phi_ref) 2^exp_f and g_i 2^exp_g in float / IEEE half, arithmetic in
+ * FP32, with the velocity and pressure moments (Eq. 22) in FP64. */
+enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16 = 2 };
+
+/* kernel choice for the step */
+enum {
+    LBM_KERNEL_AUTO = 0,  /* the autotuner picks */
+    LBM_KERNEL_FUSED = 1, /* one launch per step: pull-stream, phi tile with recomputed halo
+                             in LDS, stencil, closure, moments, collide, store */
+    LBM_KERNEL_SPLIT = 2  /* two launches per step: phi plane, then stencil + collide */
+};
+
+#define LBM_EXP_AUTO (-1000) /* let the library choose a storage exponent */
+
+/* Per-instance problem parameters. */
+typedef struct {
+    int32_t nx, ny;           /* lattice size, each >= 3 */
+    int32_t bc_ylo, bc_yhi;   /* LBM_BC_*; PERIODIC must be set on both sides or on neither */
+    int32_t visc_law;         /* LBM_VISC_* */
+    int32_t reserved0;
+    double rho_l, rho_g;      /* phase densities, > 0 (Eq. 13) */
+    double nu_l, nu_g;        /* phase kinematic viscosities, > 0 */
+    double sigma;             /* surface tension, >= 0 (Eq. 7) */
+    double W;                 /* interface width, > 0 (Eqs. 3, 7) */
+    double M;                 /* mobility, > 0; tau_phi = M / c_s^2 + 0.5 (Eq. 14) */
+    double Gx, Gy;            /* body-force density (Eq. 4b) */
+    double phi_ref;           /* F32/F16: reference of the stored f deviation; F64: ignored */
+    int32_t exp_f, exp_g;     /* F16/F32 storage exponents, or LBM_EXP_AUTO */
+} lbm_params;
+
+/* Context-wide options. */
+typedef struct {
+    int32_t storage;          /* LBM_STORE_*, the same for every instance */
+    int32_t kernel;           /* LBM_KERNEL_* */
+    int32_t tile_rows;        /* rows per fused-kernel tile (4, 8 or 16); 0 = autotune/default */
+    int32_t use_graph;        /* 1: lbm_step replays captured HIP graphs of two steps */
+    int32_t check_every;      /* > 0: every that many steps lbm_step checks for non-finite
+                                 values and returns LBM_ERR_NONFINITE (synchronises) */
+    int32_t reserved[3];
+} lbm_options;
+
+/* Integral diagnostics of one instance, FP64 accumulation in a fixed order. */
+typedef struct {
+    double sum_phi;             /* sum of phi (conserved, Sec. 2.3 remarks) */
+    double sum_rho;             /* sum of rho */
+    double kinetic;             /* sum of rho |u|^2 / 2 */
+    double max_u;               /* max |u| */
+    double min_rho;
+    double min_phi, max_phi;
+    double p_in, p_out;         /* mean p inside r < r_in / outside r > r_out of (xc, yc),
+                                   periodic distance; 0 if the set is empty */
+    double interface_crossings; /* x- and y-neighbour pairs on different sides of phi = 0.5 */
+    double spread_radius;       /* on row y_row: max |x* - xc| over linear-interpolated
+                                   crossings x* of phi = 0.5 between neighbours; 0 if none */
+    int64_t nonfinite;          /* nodes with a non-finite phi, rho, p or u */
+    int64_t step;               /* steps taken so far */
+} lbm_diag;
+
+/* Creates a context of n_inst instances.  p[k] are the parameters of instance k; phi0[k],
+ * ux0[k], uy0[k] its initial fields (host, double, [ny][nx]), copied during the call.
+ * The initial distributions are the equilibria f = f^eq(phi0, u0) (Eq. 9) and
+ * g = g^eq(p = 0, u0) (Eq. 16) with rho = rho(phi0), and phi u of the previous step is
+ * phi0 u0.  opt may be NULL (F32 storage, autotuned fused kernel, graphs on).  hip_stream
+ * is a hipStream_t the work is ordered on (NULL: the library creates its own).
+ * On success *out receives the context. */
+int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
+             const double* const* phi0, const double* const* ux0, const double* const* uy0,
+             void* hip_stream, lbm_ctx** out);
+
+/* Advances every instance by nsteps >= 0 time steps (Eqs. 8 and 15, collide then stream).
+ * Stream-ordered: returns before completion unless check_every > 0. */
+int lbm_step(lbm_ctx* c, int64_t nsteps);
+
+/* Macroscopic fields of instance inst on the current state: phi (Eq. 12), rho (Eq. 13),
+ * p (Eq. 22b), u (Eq. 22a) -- exactly the values the next collision uses.  Host buffers of
+ * nx*ny doubles each, [ny][nx]; any may be NULL.  Synchronises. */
+int lbm_moments(lbm_ctx* c, int32_t inst, double* phi, double* rho, double* p, double* ux,
+                double* uy);
+
+/* Same, into a caller-owned device buffer of 5*nx*ny doubles laid out as the planes
+ * phi, rho, p, ux, uy.  Stream-ordered, does not synchronise. */
+int lbm_moments_device(lbm_ctx* c, int32_t inst, double* d_out5);
+
+/* Integral diagnostics of instance inst.  mask = {xc, yc, r_in, r_out, y_row} (may be NULL:
+ * all zero, y_row < 0 disables the spreading radius).  Synchronises. */
+int lbm_reduce(lbm_ctx* c, int32_t inst, const double* mask, lbm_diag* out);
+
+/* Serialises the complete state (distributions, phi u of the previous step, step count).
+ * With buf == NULL only *bytes is set to the size needed.  Synchronises. */
+int lbm_get_state(lbm_ctx* c, void* buf, size_t* bytes);
+
+/* Restores a state written by lbm_get_state of a context with the same instances and
+ * storage.  Synchronises. */
+int lbm_set_state(lbm_ctx* c, const void* buf, size_t bytes);
+
+/* Number of steps taken; the tile rows and kernel the context runs with. */
+int lbm_info(const lbm_ctx* c, int64_t* step, int32_t* kernel, int32_t* tile_rows);
+
+/* Message of the last error of c, or of the calling thread if c is NULL. */
+const char* lbm_last_error(const lbm_ctx* c);
+
+/* Frees every device and host resource of c; NULL is ignored. */
+void lbm_destroy(lbm_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

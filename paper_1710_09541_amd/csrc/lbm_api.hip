@@ -1,0 +1,697 @@
+// Host runtime and C-ABI of liblbm_hip (see include/lbm.h): parameter validation, derived
+// constants, SoA buffer layout, tile work-lists, HIP-graph replay of step pairs, the
+// autotuner, moments, reductions and state save/restore.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_device.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_thread_err;
+
+constexpr uint64_t STATE_MAGIC = 0x4c424d5046534154ull;  // "LBMPFSAT"
+constexpr int STATE_VERSION = 1;
+constexpr int PLANE_PAD = 192;  // elements added to each plane: breaks power-of-two plane strides
+
+struct Instance {
+    lbm_params p;
+    InstDev d;
+    int64_t n_nodes;
+    int tile_begin_k1, tile_count_k1;  // this instance's tiles in the 4-row list
+};
+
+struct TileList {
+    int rows = 0;
+    int count = 0;
+    TileDesc* dev = nullptr;
+};
+
+struct StateHeader {
+    uint64_t magic;
+    int32_t version, storage, n_inst, streamed;
+    int64_t step;
+    int32_t cur, reserved;
+    uint64_t bytes_dist, bytes_q;
+    uint64_t total;
+};
+
+}  // namespace
+
+struct lbm_ctx {
+    std::vector<Instance> inst;
+    lbm_options opt;
+    int storage = STORE_F32;
+    size_t esize = 4;          // bytes per stored distribution value
+    size_t qsize = 4;          // bytes per q / phi value (compute type)
+    int64_t dist_elems = 0;    // elements of one distribution set (all instances, 9 planes)
+    int64_t q_elems = 0;       // 2 planes per instance
+    int64_t phi_elems = 0;     // 1 plane per instance
+    void* f[2] = {nullptr, nullptr};
+    void* g[2] = {nullptr, nullptr};
+    void* q = nullptr;
+    void* q_tune = nullptr;
+    void* phiplane = nullptr;
+    InstDev* d_insts = nullptr;
+    TileList lists[3];         // 4, 8, 16 rows
+    double* mom = nullptr;     // 5 * max nodes, moments scratch
+    double* partials = nullptr;
+    double* red_out = nullptr;
+    double* h_red = nullptr;   // pinned
+    int64_t max_nodes = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // two steps starting from buffer 0 / 1
+    int cur = 0;               // buffer holding the current state
+    bool streamed = true;      // the current state is still the initial, streamed one
+    int64_t step = 0;
+    int kernel = LBM_KERNEL_FUSED;
+    int tile_rows = 8;
+    std::string err;
+};
+
+namespace {
+
+int fail(lbm_ctx* c, int code, const std::string& msg) {
+    g_thread_err = msg;
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(lbm_ctx* c, hipError_t e, const char* what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(c, LBM_ERR_DEVICE, m);
+}
+
+#define HIPCHK(c, call)                                   \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(c, e_, #call); \
+    } while (0)
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+int list_index(int rows) { return rows == 4 ? 0 : (rows == 8 ? 1 : (rows == 16 ? 2 : -1)); }
+
+std::string check_params(const lbm_params& p, int k) {
+    char b[256];
+    auto bad = [&](const char* what) {
+        snprintf(b, sizeof b, "instance %d: %s", k, what);
+        return std::string(b);
+    };
+    if (p.nx < 3 || p.ny < 3) return bad("nx and ny must be >= 3");
+    if (p.bc_ylo < 0 || p.bc_ylo > 2 || p.bc_yhi < 0 || p.bc_yhi > 2)
+        return bad("unknown boundary type");
+    if ((p.bc_ylo == LBM_BC_PERIODIC) != (p.bc_yhi == LBM_BC_PERIODIC))
+        return bad("periodic must be set on both y sides or on neither");
+    if (p.visc_law < 0 || p.visc_law > 2) return bad("unknown viscosity law");
+    if (!(p.rho_l > 0) || !(p.rho_g > 0)) return bad("densities must be > 0");
+    if (!(p.nu_l > 0) || !(p.nu_g > 0)) return bad("viscosities must be > 0");
+    if (!(p.W > 0)) return bad("W must be > 0");
+    if (!(p.M > 0)) return bad("M must be > 0");
+    if (!(p.sigma >= 0)) return bad("sigma must be >= 0");
+    if (!isfinite(p.Gx) || !isfinite(p.Gy) || !isfinite(p.phi_ref)) return bad("non-finite input");
+    const int64_t pitch = round_up(p.nx, TILE_X);
+    if (9 * ((int64_t)p.ny * pitch + PLANE_PAD) >= (int64_t)1 << 31)
+        return bad("grid too large for one instance");
+    return std::string();
+}
+
+int pick_exponent(int given, double bound, int storage) {
+    if (given != LBM_EXP_AUTO) return given;
+    if (storage != STORE_F16) return 0;
+    // keep 32x head-room below the largest half (65504)
+    int e = (int)floor(log2(65504.0 / (32.0 * bound)));
+    return std::max(-8, std::min(24, e));
+}
+
+void fill_inst(Instance& I, int storage, const double* phi0, const double* ux0, const double* uy0) {
+    const lbm_params& p = I.p;
+    InstDev& d = I.d;
+    memset(&d, 0, sizeof d);
+    d.nx = p.nx;
+    d.ny = p.ny;
+    d.pitch = (int)round_up(p.nx, TILE_X);
+    d.bc_lo = p.bc_ylo;
+    d.bc_hi = p.bc_yhi;
+    d.visc_law = p.visc_law;
+    d.plane = (int64_t)p.ny * d.pitch + PLANE_PAD;
+    d.rho_l = p.rho_l;
+    d.rho_g = p.rho_g;
+    d.drho = p.rho_l - p.rho_g;
+    d.nu_l = p.nu_l;
+    d.nu_g = p.nu_g;
+    d.inv_nu_l = 1.0 / p.nu_l;
+    d.inv_nu_g = 1.0 / p.nu_g;
+    d.mu_l = p.rho_l * p.nu_l;
+    d.mu_g = p.rho_g * p.nu_g;
+    d.kappa = 1.5 * p.sigma * p.W;      // Eq. 7
+    d.beta = 12.0 * p.sigma / p.W;
+    d.inv_w = 1.0 / p.W;
+    const double tau_f = 3.0 * p.M + 0.5;  // Eq. 14
+    d.inv_tau_f = 1.0 / tau_f;
+    d.cf = 1.0 - 0.5 / tau_f;
+    d.Gx = p.Gx;
+    d.Gy = p.Gy;
+    d.phi_ref = storage == STORE_F64 ? 0.0 : p.phi_ref;
+    // bound of the initial g (equilibria at p = 0), floor for fluids at rest
+    double gb = 1e-3 * std::max(p.rho_l, p.rho_g);
+    const int64_t n = (int64_t)p.nx * p.ny;
+    for (int64_t k = 0; k < n; ++k) {
+        const double rho = phi0[k] * d.drho + p.rho_g;
+        const double u = fabs(ux0[k]) + fabs(uy0[k]);
+        gb = std::max(gb, rho * (3.0 * u + 4.5 * u * u) * (4.0 / 9.0));
+    }
+    const int ef = pick_exponent(p.exp_f, 0.5, storage);
+    const int eg = pick_exponent(p.exp_g, gb, storage);
+    d.scale_f = ldexp(1.0, ef);
+    d.inv_scale_f = ldexp(1.0, -ef);
+    d.scale_g = ldexp(1.0, eg);
+    d.inv_scale_g = ldexp(1.0, -eg);
+    I.p.exp_f = ef;
+    I.p.exp_g = eg;
+    I.n_nodes = n;
+}
+
+std::vector<TileDesc> build_tiles(const std::vector<Instance>& v, int rows) {
+    std::vector<TileDesc> t;
+    for (size_t k = 0; k < v.size(); ++k)
+        for (int y0 = 0; y0 < v[k].p.ny; y0 += rows)
+            for (int x0 = 0; x0 < v[k].p.nx; x0 += TILE_X) t.push_back({(int32_t)k, x0, y0, 0});
+    return t;
+}
+
+void free_all(lbm_ctx* c) {
+    for (int i = 0; i < 2; ++i) {
+        if (c->graph[i]) hipGraphExecDestroy(c->graph[i]);
+        c->graph[i] = nullptr;
+        if (c->f[i]) hipFree(c->f[i]);
+        if (c->g[i]) hipFree(c->g[i]);
+        c->f[i] = c->g[i] = nullptr;
+    }
+    void* ptrs[] = {c->q, c->q_tune, c->phiplane, c->d_insts, c->mom, c->partials, c->red_out};
+    for (void* p : ptrs)
+        if (p) hipFree(p);
+    for (auto& l : c->lists)
+        if (l.dev) hipFree(l.dev);
+    if (c->h_red) hipHostFree(c->h_red);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+}
+
+StepArgs step_args(lbm_ctx* c, int src, bool pull, int rows, bool split, void* q) {
+    StepArgs a;
+    const TileList& L = c->lists[list_index(rows)];
+    a.insts = c->d_insts;
+    a.tiles = L.dev;
+    a.ntiles = L.count;
+    a.tile_rows = rows;
+    a.pull = pull;
+    a.split = split;
+    a.fsrc = c->f[src];
+    a.gsrc = c->g[src];
+    a.fdst = c->f[1 - src];
+    a.gdst = c->g[1 - src];
+    a.q = q;
+    a.phiplane = c->phiplane;
+    a.stream = c->stream;
+    return a;
+}
+
+int launch_one(lbm_ctx* c, hipStream_t st) {
+    StepArgs a;
+    if (c->streamed)
+        a = step_args(c, c->cur, false, 4, false, c->q);
+    else
+        a = step_args(c, c->cur, true, c->tile_rows, c->kernel == LBM_KERNEL_SPLIT, c->q);
+    a.stream = st;
+    hipError_t e = launch_step(c->storage, a);
+    if (e != hipSuccess) return hip_fail(c, e, "step launch");
+    c->cur = 1 - c->cur;
+    c->streamed = false;
+    return LBM_OK;
+}
+
+void drop_graphs(lbm_ctx* c) {
+    for (int i = 0; i < 2; ++i) {
+        if (c->graph[i]) hipGraphExecDestroy(c->graph[i]);
+        c->graph[i] = nullptr;
+    }
+}
+
+// captures two consecutive steps starting from buffer `from`
+int capture_pair(lbm_ctx* c, int from) {
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    const int save_cur = c->cur;
+    const bool save_streamed = c->streamed;
+    c->cur = from;
+    c->streamed = false;
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = launch_one(c, c->cap_stream);
+    if (rc == LBM_OK) rc = launch_one(c, c->cap_stream);
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &gr);
+    c->cur = save_cur;
+    c->streamed = save_streamed;
+    if (rc != LBM_OK) {
+        if (gr) hipGraphDestroy(gr);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&c->graph[from], gr, nullptr, nullptr, 0);
+    hipGraphDestroy(gr);
+    if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+    return LBM_OK;
+}
+
+int moments_to(lbm_ctx* c, int inst, double* out) {
+    const Instance& I = c->inst[inst];
+    StepArgs a = step_args(c, c->cur, !c->streamed, 4, false, c->q);
+    a.tiles = c->lists[0].dev + I.tile_begin_k1;
+    a.ntiles = I.tile_count_k1;
+    hipError_t e = launch_moments(c->storage, a, out);
+    if (e != hipSuccess) return hip_fail(c, e, "moments launch");
+    return LBM_OK;
+}
+
+int reduce_inst(lbm_ctx* c, int inst, const double* mask, double* res /*12*/) {
+    int rc = moments_to(c, inst, c->mom);
+    if (rc) return rc;
+    const Instance& I = c->inst[inst];
+    double m[5] = {0, 0, 0, 0, -1};
+    if (mask) memcpy(m, mask, sizeof m);
+    hipError_t e = launch_reduce(c->mom, I.p.nx, I.p.ny, I.p.bc_ylo == LBM_BC_PERIODIC, m,
+                                 c->partials, c->red_out, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "reduce launch");
+    HIPCHK(c, hipMemcpyAsync(c->h_red, c->red_out, 12 * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    memcpy(res, c->h_red, 12 * sizeof(double));
+    return LBM_OK;
+}
+
+int check_finite(lbm_ctx* c) {
+    for (size_t k = 0; k < c->inst.size(); ++k) {
+        double r[12];
+        int rc = reduce_inst(c, (int)k, nullptr, r);
+        if (rc) return rc;
+        if (r[11] > 0) {
+            char b[160];
+            snprintf(b, sizeof b, "instance %zu: %.0f nodes with non-finite values at step %lld", k,
+                     r[11], (long long)c->step);
+            return fail(c, LBM_ERR_NONFINITE, b);
+        }
+    }
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+// Times each candidate (kernel, tile rows) on the context's own data: repeated launches
+// from the current buffer into the other one, with a scratch copy of phi u, so the state
+// is left untouched.  The fastest median wins.
+int autotune(lbm_ctx* c) {
+    struct Cand {
+        int kernel, rows;
+    };
+    std::vector<Cand> cands;
+    const bool want_fused = c->opt.kernel != LBM_KERNEL_SPLIT;
+    const bool want_split = c->opt.kernel != LBM_KERNEL_FUSED;
+    const int rows_opts[3] = {4, 8, 16};
+    for (int r : rows_opts) {
+        if (c->opt.tile_rows && c->opt.tile_rows != r) continue;
+        if (c->storage == STORE_F64 && r == 16) continue;  // 16 rows of doubles spill
+        if (want_fused) cands.push_back({LBM_KERNEL_FUSED, r});
+        if (want_split) cands.push_back({LBM_KERNEL_SPLIT, r});
+    }
+    if (cands.size() == 1) {
+        c->kernel = cands[0].kernel;
+        c->tile_rows = cands[0].rows;
+        return LBM_OK;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->q_tune, c->q, c->q_elems * c->qsize, hipMemcpyDeviceToDevice,
+                             c->stream));
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    int64_t nodes = 0;
+    for (auto& I : c->inst) nodes += I.n_nodes;
+    const int reps = std::max(3, (int)std::min<int64_t>(50, 200000000 / std::max<int64_t>(nodes, 1)));
+    float best = 1e30f;
+    for (const Cand& cd : cands) {
+        StepArgs a = step_args(c, c->cur, true, cd.rows, cd.kernel == LBM_KERNEL_SPLIT, c->q_tune);
+        float t[3];
+        for (int r = 0; r < 3; ++r) {
+            hipEventRecord(e0, c->stream);
+            for (int k = 0; k < reps; ++k) {
+                hipError_t e = launch_step(c->storage, a);
+                if (e != hipSuccess) return hip_fail(c, e, "autotune launch");
+            }
+            hipEventRecord(e1, c->stream);
+            HIPCHK(c, hipEventSynchronize(e1));
+            hipEventElapsedTime(&t[r], e0, e1);
+        }
+        std::sort(t, t + 3);
+        if (t[1] < best) {
+            best = t[1];
+            c->kernel = cd.kernel;
+            c->tile_rows = cd.rows;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return LBM_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C-ABI
+
+extern "C" {
+
+int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
+             const double* const* phi0, const double* const* ux0, const double* const* uy0,
+             void* hip_stream, lbm_ctx** out) {
+    if (!out) return fail(nullptr, LBM_ERR_PARAM, "out is NULL");
+    *out = nullptr;
+    if (!p || n_inst < 1) return fail(nullptr, LBM_ERR_PARAM, "need at least one instance");
+    if (!phi0 || !ux0 || !uy0) return fail(nullptr, LBM_ERR_PARAM, "initial fields are NULL");
+    lbm_options o;
+    memset(&o, 0, sizeof o);
+    o.storage = LBM_STORE_F32;
+    o.kernel = LBM_KERNEL_AUTO;
+    o.use_graph = 1;
+    if (opt) o = *opt;
+    if (o.storage < 0 || o.storage > 2) return fail(nullptr, LBM_ERR_PARAM, "unknown storage");
+    if (o.kernel < 0 || o.kernel > 2) return fail(nullptr, LBM_ERR_PARAM, "unknown kernel");
+    if (o.tile_rows != 0 && list_index(o.tile_rows) < 0)
+        return fail(nullptr, LBM_ERR_PARAM, "tile_rows must be 0, 4, 8 or 16");
+    if (o.check_every < 0) return fail(nullptr, LBM_ERR_PARAM, "check_every must be >= 0");
+    for (int k = 0; k < n_inst; ++k) {
+        std::string m = check_params(p[k], k);
+        if (!m.empty()) return fail(nullptr, LBM_ERR_PARAM, m);
+        if (!phi0[k] || !ux0[k] || !uy0[k])
+            return fail(nullptr, LBM_ERR_PARAM, "initial field of an instance is NULL");
+    }
+
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(nullptr, LBM_ERR_ALLOC, "host allocation failed");
+    c->opt = o;
+    c->storage = o.storage;
+    c->esize = o.storage == STORE_F64 ? 8 : (o.storage == STORE_F32 ? 4 : 2);
+    c->qsize = o.storage == STORE_F64 ? 8 : 4;
+    c->inst.resize(n_inst);
+    int64_t off_dist = 0, off_q = 0, off_phi = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        Instance& I = c->inst[k];
+        I.p = p[k];
+        fill_inst(I, c->storage, phi0[k], ux0[k], uy0[k]);
+        I.d.off_dist = off_dist;
+        I.d.off_q = off_q;
+        I.d.off_phi = off_phi;
+        off_dist += round_up(9 * I.d.plane, 64);
+        off_q += round_up(2 * I.d.plane, 64);
+        off_phi += round_up(I.d.plane, 64);
+        c->max_nodes = std::max(c->max_nodes, I.n_nodes);
+    }
+    c->dist_elems = off_dist;
+    c->q_elems = off_q;
+    c->phi_elems = off_phi;
+
+    auto bail = [&](int rc) {
+        free_all(c);
+        delete c;
+        return rc;
+    };
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) {
+        fail(c, LBM_ERR_DEVICE, "no HIP device available");
+        return bail(LBM_ERR_DEVICE);
+    }
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return bail(hip_fail(c, e, "hipStreamCreate"));
+        c->own_stream = true;
+    }
+    const size_t dist_bytes = c->dist_elems * c->esize;
+    struct {
+        void** ptr;
+        size_t bytes;
+    } allocs[] = {
+        {&c->f[0], dist_bytes},
+        {&c->f[1], dist_bytes},
+        {&c->g[0], dist_bytes},
+        {&c->g[1], dist_bytes},
+        {&c->q, c->q_elems * c->qsize},
+        {&c->q_tune, c->q_elems * c->qsize},
+        {&c->phiplane, c->phi_elems * c->qsize},
+        {(void**)&c->d_insts, n_inst * sizeof(InstDev)},
+        {(void**)&c->mom, 5 * c->max_nodes * sizeof(double)},
+        {(void**)&c->partials, 1024 * 13 * sizeof(double)},
+        {(void**)&c->red_out, 16 * sizeof(double)},
+    };
+    for (auto& a : allocs) {
+        e = hipMalloc(a.ptr, a.bytes);
+        if (e != hipSuccess) {
+            fail(c, LBM_ERR_ALLOC, std::string("device allocation failed: ") + hipGetErrorString(e));
+            return bail(LBM_ERR_ALLOC);
+        }
+    }
+    e = hipHostMalloc((void**)&c->h_red, 16 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) return bail(hip_fail(c, e, "hipHostMalloc"));
+    // padding between and inside planes is never read, but keep it defined
+    for (int i = 0; i < 2; ++i) {
+        hipMemsetAsync(c->f[i], 0, dist_bytes, c->stream);
+        hipMemsetAsync(c->g[i], 0, dist_bytes, c->stream);
+    }
+    hipMemsetAsync(c->phiplane, 0, c->phi_elems * c->qsize, c->stream);
+
+    std::vector<InstDev> hd(n_inst);
+    for (int k = 0; k < n_inst; ++k) hd[k] = c->inst[k].d;
+    e = hipMemcpyAsync(c->d_insts, hd.data(), n_inst * sizeof(InstDev), hipMemcpyHostToDevice,
+                       c->stream);
+    if (e != hipSuccess) return bail(hip_fail(c, e, "copy instances"));
+    const int rows_of[3] = {4, 8, 16};
+    for (int li = 0; li < 3; ++li) {
+        std::vector<TileDesc> t = build_tiles(c->inst, rows_of[li]);
+        TileList& L = c->lists[li];
+        L.rows = rows_of[li];
+        L.count = (int)t.size();
+        e = hipMalloc((void**)&L.dev, t.size() * sizeof(TileDesc));
+        if (e != hipSuccess) return bail(hip_fail(c, e, "tile list"));
+        e = hipMemcpy(L.dev, t.data(), t.size() * sizeof(TileDesc), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return bail(hip_fail(c, e, "tile list copy"));
+        if (li == 0) {
+            int pos = 0;
+            for (int k = 0; k < n_inst; ++k) {
+                c->inst[k].tile_begin_k1 = pos;
+                while (pos < (int)t.size() && t[pos].inst == k) ++pos;
+                c->inst[k].tile_count_k1 = pos - c->inst[k].tile_begin_k1;
+            }
+        }
+    }
+    // initial fields -> device staging -> equilibrium distributions
+    double* stage = nullptr;
+    e = hipMalloc((void**)&stage, 3 * c->max_nodes * sizeof(double));
+    if (e != hipSuccess) return bail(hip_fail(c, e, "staging allocation"));
+    for (int k = 0; k < n_inst; ++k) {
+        const int64_t n = c->inst[k].n_nodes;
+        e = hipMemcpy(stage, phi0[k], n * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(stage + n, ux0[k], n * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(stage + 2 * n, uy0[k], n * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = launch_init(c->storage, c->d_insts, k, c->inst[k].p.nx, c->inst[k].p.ny, stage,
+                            stage + n, stage + 2 * n, c->f[0], c->g[0], c->q, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            hipFree(stage);
+            return bail(hip_fail(c, e, "initial state"));
+        }
+    }
+    hipFree(stage);
+    c->cur = 0;
+    c->streamed = true;
+    c->step = 0;
+    c->kernel = o.kernel == LBM_KERNEL_AUTO ? LBM_KERNEL_FUSED : o.kernel;
+    c->tile_rows = o.tile_rows ? o.tile_rows : (c->storage == STORE_F64 ? 4 : 8);
+    if (o.kernel == LBM_KERNEL_AUTO || o.tile_rows == 0) {
+        int rc = autotune(c);
+        if (rc) return bail(rc);
+    }
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return bail(hip_fail(c, e, "init synchronise"));
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int64_t nsteps) {
+    if (!c) return fail(nullptr, LBM_ERR_PARAM, "context is NULL");
+    if (nsteps < 0) return fail(c, LBM_ERR_PARAM, "nsteps must be >= 0");
+    int64_t left = nsteps;
+    while (left > 0) {
+        int64_t chunk = left;
+        if (c->opt.check_every > 0) {
+            const int64_t to_check = c->opt.check_every - (c->step % c->opt.check_every);
+            chunk = std::min(chunk, to_check);
+        }
+        int64_t done = 0;
+        while (done < chunk) {
+            if (!c->streamed && c->opt.use_graph && chunk - done >= 2) {
+                if (!c->graph[c->cur]) {
+                    int rc = capture_pair(c, c->cur);
+                    if (rc) return rc;
+                }
+                hipError_t e = hipGraphLaunch(c->graph[c->cur], c->stream);
+                if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+                done += 2;
+                c->step += 2;
+            } else {
+                int rc = launch_one(c, c->stream);
+                if (rc) return rc;
+                done += 1;
+                c->step += 1;
+            }
+        }
+        left -= chunk;
+        if (c->opt.check_every > 0 && c->step % c->opt.check_every == 0) {
+            int rc = check_finite(c);
+            if (rc) return rc;
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx* c, int32_t inst, double* phi, double* rho, double* p, double* ux,
+                double* uy) {
+    if (!c) return fail(nullptr, LBM_ERR_PARAM, "context is NULL");
+    if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, LBM_ERR_RANGE, "no such instance");
+    int rc = moments_to(c, inst, c->mom);
+    if (rc) return rc;
+    const int64_t n = c->inst[inst].n_nodes;
+    double* outs[5] = {phi, rho, p, ux, uy};
+    for (int m = 0; m < 5; ++m)
+        if (outs[m])
+            HIPCHK(c, hipMemcpyAsync(outs[m], c->mom + m * n, n * sizeof(double),
+                                     hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_moments_device(lbm_ctx* c, int32_t inst, double* d_out5) {
+    if (!c) return fail(nullptr, LBM_ERR_PARAM, "context is NULL");
+    if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, LBM_ERR_RANGE, "no such instance");
+    if (!d_out5) return fail(c, LBM_ERR_PARAM, "output is NULL");
+    return moments_to(c, inst, d_out5);
+}
+
+int lbm_reduce(lbm_ctx* c, int32_t inst, const double* mask, lbm_diag* out) {
+    if (!c) return fail(nullptr, LBM_ERR_PARAM, "context is NULL");
+    if (!out) return fail(c, LBM_ERR_PARAM, "output is NULL");
+    if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, LBM_ERR_RANGE, "no such instance");
+    double r[12];
+    int rc = reduce_inst(c, inst, mask, r);
+    if (rc) return rc;
+    out->sum_phi = r[0];
+    out->sum_rho = r[1];
+    out->kinetic = r[2];
+    out->max_u = r[3];
+    out->min_rho = r[4];
+    out->min_phi = r[5];
+    out->max_phi = r[6];
+    out->p_in = r[7];
+    out->p_out = r[8];
+    out->interface_crossings = r[9];
+    out->spread_radius = r[10];
+    out->nonfinite = (int64_t)r[11];
+    out->step = c->step;
+    return LBM_OK;
+}
+
+int lbm_get_state(lbm_ctx* c, void* buf, size_t* bytes) {
+    if (!c) return fail(nullptr, LBM_ERR_PARAM, "context is NULL");
+    if (!bytes) return fail(c, LBM_ERR_PARAM, "bytes is NULL");
+    const uint64_t bd = c->dist_elems * c->esize, bq = c->q_elems * c->qsize;
+    const uint64_t total = sizeof(StateHeader) + 2 * bd + bq;
+    if (!buf) {
+        *bytes = total;
+        return LBM_OK;
+    }
+    if (*bytes < total) return fail(c, LBM_ERR_RANGE, "state buffer too small");
+    StateHeader h;
+    memset(&h, 0, sizeof h);
+    h.magic = STATE_MAGIC;
+    h.version = STATE_VERSION;
+    h.storage = c->storage;
+    h.n_inst = (int32_t)c->inst.size();
+    h.streamed = c->streamed ? 1 : 0;
+    h.step = c->step;
+    h.bytes_dist = bd;
+    h.bytes_q = bq;
+    h.total = total;
+    char* b = (char*)buf;
+    memcpy(b, &h, sizeof h);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(b + sizeof h, c->f[c->cur], bd, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(b + sizeof h + bd, c->g[c->cur], bd, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(b + sizeof h + 2 * bd, c->q, bq, hipMemcpyDeviceToHost));
+    *bytes = total;
+    return LBM_OK;
+}
+
+int lbm_set_state(lbm_ctx* c, const void* buf, size_t bytes) {
+    if (!c) return fail(nullptr, LBM_ERR_PARAM, "context is NULL");
+    if (!buf || bytes < sizeof(StateHeader)) return fail(c, LBM_ERR_PARAM, "state buffer too small");
+    StateHeader h;
+    memcpy(&h, buf, sizeof h);
+    const uint64_t bd = c->dist_elems * c->esize, bq = c->q_elems * c->qsize;
+    if (h.magic != STATE_MAGIC || h.version != STATE_VERSION)
+        return fail(c, LBM_ERR_PARAM, "not a state of this library");
+    if (h.storage != c->storage || h.n_inst != (int32_t)c->inst.size() || h.bytes_dist != bd ||
+        h.bytes_q != bq || h.total != bytes)
+        return fail(c, LBM_ERR_PARAM, "state does not match this context");
+    const char* b = (const char*)buf;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->f[0], b + sizeof h, bd, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->g[0], b + sizeof h + bd, bd, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->q, b + sizeof h + 2 * bd, bq, hipMemcpyHostToDevice));
+    c->cur = 0;
+    c->streamed = h.streamed != 0;
+    c->step = h.step;
+    return LBM_OK;
+}
+
+int lbm_info(const lbm_ctx* c, int64_t* step, int32_t* kernel, int32_t* tile_rows) {
+    if (!c) return fail(nullptr, LBM_ERR_PARAM, "context is NULL");
+    if (step) *step = c->step;
+    if (kernel) *kernel = c->kernel;
+    if (tile_rows) *tile_rows = c->tile_rows;
+    return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_ctx* c) {
+    return c ? c->err.c_str() : g_thread_err.c_str();
+}
+
+void lbm_destroy(lbm_ctx* c) {
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// Device-side data structures shared by the kernels and the host runtime of liblbm_hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+enum { BC_PERIODIC = 0, BC_WALL = 1, BC_OPEN = 2 };
+enum { VISC_LINEAR = 0, VISC_INVERSE = 1, VISC_STEP_MU = 2 };
+enum { STORE_F64 = 0, STORE_F32 = 1, STORE_F16 = 2 };
+
+constexpr int TILE_X = 64;      // tile width = one wavefront of 64 lanes
+constexpr int BLOCK = 256;      // 4 wavefronts; a tile row group is 4 rows
+constexpr int NXCD = 8;         // MI355X: 8 accelerator complex dies, each with its own L2
+
+// Per-instance constants, read with uniform (scalar) loads.  Distances are in elements.
+struct InstDev {
+    int32_t nx, ny, pitch, bc_lo, bc_hi, visc_law;
+    int64_t off_dist;   // offset of this instance's plane 0 in the f and g arrays
+    int64_t off_q;      // offset of its first (phi u) plane in the q array
+    int64_t off_phi;    // offset of its phi plane (split kernel)
+    int64_t plane;      // ny * pitch
+    double rho_l, rho_g, drho;      // drho = rho_l - rho_g
+    double nu_l, nu_g, inv_nu_l, inv_nu_g, mu_l, mu_g;
+    double kappa, beta, inv_w;      // k = 1.5 sigma W, beta = 12 sigma / W, 1 / W
+    double inv_tau_f, cf;           // 1 / tau_phi and 1 - 1 / (2 tau_phi)
+    double Gx, Gy;
+    double phi_ref;                 // stored f is (f_i - w_i phi_ref) * scale_f
+    double scale_f, inv_scale_f, scale_g, inv_scale_g;
+};
+
+// One tile of TILE_X x rows nodes of one instance.
+struct TileDesc {
+    int32_t inst, x0, y0, pad;
+};
+
+}  // namespace lbm
+
+namespace lbm {
+
+// Arguments of one step launch over a tile list.
+struct StepArgs {
+    const InstDev* insts;
+    const TileDesc* tiles;
+    int ntiles;
+    int tile_rows;      // 4, 8 or 16
+    bool pull;          // false only for the first step (initial state in streamed form)
+    bool split;         // two launches: phi plane, then stencil + collide
+    const void* fsrc;
+    const void* gsrc;
+    void* fdst;
+    void* gdst;
+    void* q;
+    void* phiplane;
+    hipStream_t stream;
+};
+
+hipError_t launch_step(int storage, const StepArgs& a);
+hipError_t launch_moments(int storage, const StepArgs& a, double* out);
+hipError_t launch_init(int storage, const InstDev* insts, int inst, int nx, int ny,
+                       const double* phi0, const double* ux0, const double* uy0, void* f, void* g,
+                       void* q, hipStream_t st);
+int reduce_blocks(int64_t n);
+hipError_t launch_reduce(const double* mom, int nx, int ny, int periodic_y, const double* mask,
+                         double* partials, double* out, hipStream_t st);
+
+}  // namespace lbm

@@ -1,0 +1,40 @@
+"""Helpers shared by the GPU parity tests: run a case on the oracle and on the HIP library
+and measure the max-norm error of each field, normalised as
+    E_q = max |q - q_oracle| / max(max |q_oracle|, q_scale)
+with q_scale = 1 for phi, u_scale for u and p_scale for p (set per case)."""
+import numpy as np
+
+from oracle.oracle import OracleSim
+from paper_1710_09541_amd import lbm
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "f16": 1e-3}
+
+
+def run_oracle(case, steps):
+    s = OracleSim(case, case["phi0"], case["ux0"], case["uy0"])
+    s.step(steps)
+    return s.moments()
+
+
+def run_hip(case, steps, storage, **kw):
+    with lbm.Simulation(case, storage=storage, **kw) as sim:
+        sim.step(steps)
+        return sim.moments()
+
+
+def errors(case, got, ref):
+    u_ref = np.sqrt(ref["ux"] ** 2 + ref["uy"] ** 2)
+    scale_u = max(float(u_ref.max()), case["u_scale"])
+    e = {
+        "phi": float(np.max(np.abs(got["phi"] - ref["phi"]))) / max(float(np.abs(ref["phi"]).max()), 1.0),
+        "u": max(float(np.max(np.abs(got["ux"] - ref["ux"]))),
+                 float(np.max(np.abs(got["uy"] - ref["uy"])))) / scale_u,
+        "p": float(np.max(np.abs(got["p"] - ref["p"]))) / max(float(np.abs(ref["p"]).max()), case["p_scale"]),
+        "rho": float(np.max(np.abs(got["rho"] - ref["rho"]) / ref["rho"])),
+    }
+    return e
+
+
+def report(name, storage, e):
+    print("[parity] %-28s %-4s phi %.2e  u %.2e  p %.2e  rho %.2e  (tol %.0e)"
+          % (name, storage, e["phi"], e["u"], e["p"], e["rho"], TOL[storage]), flush=True)

@@ -1,0 +1,108 @@
+"""Host-only checks of the C-ABI library: it loads, exports every entry point the header
+declares, its ctypes structures match the C layout, and parameter validation reports
+errors before touching a device (so these run without a GPU)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1710_09541_amd import cases, lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(lbm_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_binding_names():
+    assert declared_functions() == sorted(lbm.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = lbm.load()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", lbm.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (lbm_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+def _c_layout(struct, fields, tmp_path):
+    src = tmp_path / "layout.c"
+    body = "".join('printf("%s %%zu\\n", offsetof(%s, %s));\n' % (f, struct, f) for f in fields)
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lbm.h"\nint main(void){\n'
+                   + body + 'printf("sizeof %%zu\\n", sizeof(%s));\nreturn 0;}\n' % struct)
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    return dict((k, int(v)) for k, v in (line.split() for line in out.strip().splitlines()))
+
+
+@pytest.mark.parametrize("cls", [lbm.lbm_params, lbm.lbm_options, lbm.lbm_diag])
+def test_ctypes_layout_matches_header(cls, tmp_path):
+    fields = [f for f, _ in cls._fields_ if not f.startswith("reserved")]
+    lay = _c_layout(cls.__name__, fields, tmp_path)
+    for f in fields:
+        assert getattr(cls, f).offset == lay[f], f
+    assert C.sizeof(cls) == lay["sizeof"]
+
+
+def _init(case, **kw):
+    return lbm.lbm_init([lbm.make_params(case)], lbm.make_options(**kw), [case["phi0"]],
+                        [case["ux0"]], [case["uy0"]])
+
+
+@pytest.mark.parametrize("key,value", [("nx", 2), ("ny", 1), ("rho_g", 0.0), ("W", 0.0),
+                                       ("M", -1.0), ("nu_l", 0.0), ("visc_law", 9),
+                                       ("sigma", -1.0), ("Gx", float("nan"))])
+def test_invalid_parameters_rejected_before_device(key, value):
+    c = cases.static_drop(16, 16, R=4)
+    c[key] = value
+    with pytest.raises(lbm.LbmError) as e:
+        _init(c)
+    assert e.value.code == lbm.LBM_ERR_PARAM
+    assert lbm.lbm_last_error()
+
+
+def test_invalid_boundary_and_options_rejected():
+    c = cases.static_drop(16, 16, R=4)
+    c["bc_ylo"] = lbm.LBM_BC_WALL           # periodic on one side only
+    with pytest.raises(lbm.LbmError) as e:
+        _init(c)
+    assert e.value.code == lbm.LBM_ERR_PARAM and "periodic" in lbm.lbm_last_error()
+    c = cases.static_drop(16, 16, R=4)
+    for kw in ({"storage": 7}, {"tile_rows": 5}, {"kernel": 9}, {"check_every": -1}):
+        with pytest.raises(lbm.LbmError) as e:
+            _init(c, **kw)
+        assert e.value.code == lbm.LBM_ERR_PARAM
+
+
+def test_null_context_calls():
+    L = lbm.load()
+    assert L.lbm_step(None, 1) == lbm.LBM_ERR_PARAM
+    assert L.lbm_info(None, None, None, None) == lbm.LBM_ERR_PARAM
+    assert L.lbm_reduce(None, 0, None, None) == lbm.LBM_ERR_PARAM
+    L.lbm_destroy(None)
+    assert lbm.lbm_last_error()
+
+
+def test_no_device_reported_as_device_error():
+    """On a machine without a GPU a valid parameter set fails with LBM_ERR_DEVICE."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    c = cases.static_drop(16, 16, R=4)
+    with pytest.raises(lbm.LbmError) as e:
+        _init(c)
+    assert e.value.code == lbm.LBM_ERR_DEVICE
