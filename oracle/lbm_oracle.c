@@ -43,7 +43,10 @@ static const double WGT[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0
                               1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 /* opposite direction: c_opp(i) = -c_i */
 static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-static const double CS2 = 1.0 / 3.0;
+/* c_s^2 = 1/3 (c = 1); its reciprocal 3 and the derived factors 1/(2 c_s^4) = 9/2,
+ * 1/(2 c_s^2) = 3/2 and c_s^2/(1 - w_0) = 3/5 are written as exact constants, so no rounded
+ * 1/3 enters the arithmetic. */
+static const double INV_CS2 = 3.0;
 
 enum { ORC_PERIODIC = 0, ORC_WALL = 1, ORC_OPEN = 2 };
 enum { ORC_NU_LINEAR = 0, ORC_NU_INVERSE = 1, ORC_MU_STEP = 2 };
@@ -79,7 +82,7 @@ typedef struct {
 static void feq_node(double phi, double ux, double uy, double out[9]) {
     for (int i = 0; i < 9; ++i) {
         double cu = CX[i] * ux + CY[i] * uy;
-        out[i] = WGT[i] * phi * (1.0 + cu / CS2);
+        out[i] = WGT[i] * phi * (1.0 + cu * INV_CS2);
     }
 }
 
@@ -87,22 +90,23 @@ static void feq_node(double phi, double ux, double uy, double out[9]) {
 static double s_i(int i, double ux, double uy) {
     double cu = CX[i] * ux + CY[i] * uy;
     double uu = ux * ux + uy * uy;
-    return WGT[i] * (cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+    return WGT[i] * (cu * INV_CS2 + cu * cu * 4.5 - uu * 1.5);
 }
 
 /* g_i^eq: p/c_s^2 (w_0 - 1) + rho s_0 for i = 0, p/c_s^2 w_i + rho s_i otherwise  (Eq. 16) */
 static void geq_node(double p, double rho, double ux, double uy, double out[9]) {
-    out[0] = p / CS2 * (WGT[0] - 1.0) + rho * s_i(0, ux, uy);
-    for (int i = 1; i < 9; ++i) out[i] = p / CS2 * WGT[i] + rho * s_i(i, ux, uy);
+    out[0] = p * INV_CS2 * (WGT[0] - 1.0) + rho * s_i(0, ux, uy);
+    for (int i = 1; i < 9; ++i) out[i] = p * INV_CS2 * WGT[i] + rho * s_i(i, ux, uy);
 }
 
-/* F_i = (1 - 1/(2 tau_f)) w_i c_i.[d_t(phi u) + c_s^2 lambda n] / c_s^2  (Eq. 11) */
+/* F_i = (1 - 1/(2 tau_f)) w_i c_i.[d_t(phi u) + c_s^2 lambda n] / c_s^2  (Eq. 11),
+ * i.e. (1 - 1/(2 tau_f)) w_i c_i.[d_t(phi u) / c_s^2 + lambda n] */
 static void fsource_node(double tau_f, double dtx, double dty, double lambda, double nx_,
                          double ny_, double out[9]) {
-    double vx = dtx + CS2 * lambda * nx_;
-    double vy = dty + CS2 * lambda * ny_;
+    double vx = dtx * INV_CS2 + lambda * nx_;
+    double vy = dty * INV_CS2 + lambda * ny_;
     for (int i = 0; i < 9; ++i)
-        out[i] = (1.0 - 1.0 / (2.0 * tau_f)) * WGT[i] * (CX[i] * vx + CY[i] * vy) / CS2;
+        out[i] = (1.0 - 1.0 / (2.0 * tau_f)) * WGT[i] * (CX[i] * vx + CY[i] * vy);
 }
 
 /* G_i = (1 - 1/(2 tau_g)) w_i [c_i.F / c_s^2 + (rho_l - rho_g) u grad(phi) : c_i c_i / c_s^2]
@@ -113,7 +117,7 @@ static void gforce_node(double tau_g, double Fx, double Fy, double drho, double 
         double cF = CX[i] * Fx + CY[i] * Fy;
         double cu = CX[i] * ux + CY[i] * uy;
         double cgp = CX[i] * dpx + CY[i] * dpy;
-        out[i] = (1.0 - 1.0 / (2.0 * tau_g)) * WGT[i] * (cF / CS2 + drho * cu * cgp / CS2);
+        out[i] = (1.0 - 1.0 / (2.0 * tau_g)) * WGT[i] * (cF * INV_CS2 + drho * cu * cgp * INV_CS2);
     }
 }
 
@@ -161,9 +165,9 @@ static void stencil_node(const orc_params* p, const double* phi, int x, int y, d
         sy += WGT[i] * CY[i] * v;
         sl += 2.0 * WGT[i] * (v - c);
     }
-    *gx = sx / CS2;
-    *gy = sy / CS2;
-    *lap = sl / CS2;
+    *gx = sx * INV_CS2;
+    *gy = sy * INV_CS2;
+    *lap = sl * INV_CS2;
 }
 
 /* --------------------------------------------------------------- node closure */
@@ -195,7 +199,7 @@ static void closure_node(const orc_sim* s, double phi, double dpx, double dpy, d
         o->ny = 0.0;
     }
     double nu = viscosity(p, phi, o->rho);
-    o->tau_g = nu / CS2 + 0.5;                                                /* Eq. 23 */
+    o->tau_g = nu * INV_CS2 + 0.5;                                            /* Eq. 23 */
     o->Fx = o->mu_phi * dpx + p->Gx;                                          /* Eqs. 5, 19 */
     o->Fy = o->mu_phi * dpy + p->Gy;
     /* Eq. 22a: rho u = sum_i c_i g_i + 0.5 F */
@@ -210,8 +214,7 @@ static void closure_node(const orc_sim* s, double phi, double dpx, double dpy, d
     double sg = 0.0;
     for (int i = 1; i < 9; ++i) sg += g[i];
     double ugp = o->ux * dpx + o->uy * dpy;
-    o->p = CS2 / (1.0 - WGT[0]) *
-           (sg + 0.5 * (p->rho_l - p->rho_g) * ugp + o->rho * s_i(0, o->ux, o->uy));
+    o->p = 0.6 * (sg + 0.5 * (p->rho_l - p->rho_g) * ugp + o->rho * s_i(0, o->ux, o->uy));
 }
 
 static void compute_phi(orc_sim* s) {
@@ -340,7 +343,7 @@ orc_sim* orc_create(const orc_params* p, const double* phi0, const double* ux0,
     if (!s) return NULL;
     s->p = *p;
     s->n = (int64_t)p->nx * p->ny;
-    s->tau_f = p->M / CS2 + 0.5;                 /* Eq. 14 */
+    s->tau_f = p->M * INV_CS2 + 0.5;             /* Eq. 14 */
     s->kappa = 1.5 * p->sigma * p->W;            /* Eq. 7 */
     s->beta = 12.0 * p->sigma / p->W;
     size_t n9 = (size_t)(9 * s->n);
@@ -464,7 +467,7 @@ void orc_closure(const orc_params* p, double phi, double dpx, double dpy, double
     orc_sim s;
     memset(&s, 0, sizeof(s));
     s.p = *p;
-    s.tau_f = p->M / CS2 + 0.5;
+    s.tau_f = p->M * INV_CS2 + 0.5;
     s.kappa = 1.5 * p->sigma * p->W;
     s.beta = 12.0 * p->sigma / p->W;
     orc_node o;
