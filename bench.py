@@ -26,8 +26,9 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS (both lattices) and % HBM roofline, FP32/FP16 vs FP64 at stated error"
 PEAK_HBM_GBS = 8000.0
 # algorithmic bytes per lattice update of the fused step: 9 f + 9 g populations read and
-# written once, plus phi u of the previous step (2 values) read and written once
-ALG_BYTES = {"f64": 36 * 8 + 4 * 8, "f32": 36 * 4 + 4 * 4, "f16": 36 * 2 + 4 * 4}
+# written once, plus the per-node state beside them read and written once: FP64 phi u of
+# the previous step (2 doubles); reduced formats the FP32 planes phi_w, p_w, ux_w, uy_w
+ALG_BYTES = {"f64": 36 * 8 + 4 * 8, "f32": 36 * 4 + 8 * 4, "f16": 36 * 2 + 8 * 4}
 KERNEL_SRC = os.path.join(ROOT, "paper_1710_09541_amd", "csrc", "lbm_kernels.hip")
 
 

@@ -52,9 +52,10 @@ enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1, LBM_BC_OPEN = 2 };
  * dynamic viscosity (mu_l for phi >= 0.5, else mu_g) with nu = mu / rho(phi) */
 enum { LBM_VISC_LINEAR = 0, LBM_VISC_INVERSE = 1, LBM_VISC_STEP_MU = 2 };
 
-/* storage of the distributions.  F64: doubles, FP64 arithmetic.  F32 / F16: the stored
- * value is (f_i - w_i phi_ref) 2^exp_f and g_i 2^exp_g in float / IEEE half, arithmetic in
- * FP32, with the velocity and pressure moments (Eq. 22) in FP64. */
+/* storage of the distributions.  F64: doubles, FP64 arithmetic.  F32 / F16: float / IEEE
+ * half holding rest deviations (f_i - w_i phi_w) 2^exp_f, phi_w the order parameter of the
+ * node that wrote the slot (kept in an FP32 phi plane), and g_i 2^exp_g; arithmetic in
+ * FP32, with phi-to-rho and the velocity and pressure moments (Eqs. 13, 22) in FP64. */
 enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16 = 2 };
 
 /* kernel choice for the step */
@@ -79,8 +80,8 @@ typedef struct {
     double W;                 /* interface width, > 0 (Eqs. 3, 7) */
     double M;                 /* mobility, > 0; tau_phi = M / c_s^2 + 0.5 (Eq. 14) */
     double Gx, Gy;            /* body-force density (Eq. 4b) */
-    double phi_ref;           /* F32/F16: reference of the stored f deviation; F64: ignored */
-    int32_t exp_f, exp_g;     /* F16/F32 storage exponents, or LBM_EXP_AUTO */
+    int32_t exp_f, exp_g;     /* F16/F32 storage exponents, or LBM_EXP_AUTO (F16: from the
+                                 initial fields; F32: 0); ignored for F64 */
 } lbm_params;
 
 /* Context-wide options. */

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm_hip.so")
-SOURCES = ["lbm_kernels.hip", "lbm_api.hip"]
+SOURCES = ["lbm_kernels.hip", "lbm_reduce.hip", "lbm_api.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

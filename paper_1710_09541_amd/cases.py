@@ -157,7 +157,8 @@ def batch_ensemble(n=256, seed=1, lo=32, hi=512):
     Poiseuille channel with density ratio drawn from {10, 100, 1000}; grids uniform in
     [lo, hi] on each axis.  Drops: R = r min(nx, ny), r ~ U[0.15, 0.35], W = 4,
     sigma = 0.01, nu = 0.1, M = 0.1.  Channels: W = 5, sigma = 0.001, nu_l = 0.1,
-    nu_g / nu_l = 10 at ratio 1000 else 1, u_max = 1e-3, analytic start, step mu."""
+    nu_g / nu_l = 10 at ratio 1000 else 1, u_max = 1e-3, analytic start, step mu, and
+    an even row count (ny rounded up)."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(n):
@@ -169,6 +170,10 @@ def batch_ensemble(n=256, seed=1, lo=32, hi=512):
             out.append(static_drop(nx, ny, R=r * min(nx, ny), W=4.0, ratio=ratio, sigma=0.01,
                                    nu=0.1, M=0.1))
         else:
+            # an even number of rows puts the interface between two nodes; with an odd
+            # number a node would sit exactly on phi = 0.5, where the step viscosity law
+            # switches and rounding alone decides the branch
+            ny += ny % 2
             nu_g = 1.0 if ratio == 1000.0 else 0.1
             out.append(layered_poiseuille(nx, ny, ratio=ratio, nu_l=0.1, nu_g=nu_g, W=5.0,
                                           sigma=0.001, M=0.1, u_max=1e-3))

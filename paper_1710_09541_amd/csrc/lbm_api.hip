@@ -22,7 +22,7 @@ namespace {
 thread_local std::string g_thread_err;
 
 constexpr uint64_t STATE_MAGIC = 0x4c424d5046534154ull;  // "LBMPFSAT"
-constexpr int STATE_VERSION = 1;
+constexpr int STATE_VERSION = 3;
 constexpr int PLANE_PAD = 192;  // elements added to each plane: breaks power-of-two plane strides
 
 struct Instance {
@@ -43,7 +43,7 @@ struct StateHeader {
     int32_t version, storage, n_inst, streamed;
     int64_t step;
     int32_t cur, reserved;
-    uint64_t bytes_dist, bytes_q;
+    uint64_t bytes_dist, bytes_q, bytes_mp;
     uint64_t total;
 };
 
@@ -54,15 +54,17 @@ struct lbm_ctx {
     lbm_options opt;
     int storage = STORE_F32;
     size_t esize = 4;          // bytes per stored distribution value
-    size_t qsize = 4;          // bytes per q / phi value (compute type)
+    size_t qsize = 4;          // bytes per split-kernel phi value (compute type)
     int64_t dist_elems = 0;    // elements of one distribution set (all instances, 9 planes)
-    int64_t q_elems = 0;       // 2 planes per instance
-    int64_t phi_elems = 0;     // 1 plane per instance
+    int64_t q_elems = 0;       // FP64 phi u: 2 double planes per instance
+    int64_t phi_elems = 0;     // split-kernel phi: 1 plane per instance
+    int64_t mp_elems = 0;      // reduced formats: 4 float planes per instance
     void* f[2] = {nullptr, nullptr};
     void* g[2] = {nullptr, nullptr};
     void* q = nullptr;
     void* q_tune = nullptr;
     void* phiplane = nullptr;
+    void* rplane[2] = {nullptr, nullptr};  // planes phi_w, p_w, u_w written with buffer i
     InstDev* d_insts = nullptr;
     TileList lists[3];         // 4, 8, 16 rows
     double* mom = nullptr;     // 5 * max nodes, moments scratch
@@ -122,7 +124,7 @@ std::string check_params(const lbm_params& p, int k) {
     if (!(p.W > 0)) return bad("W must be > 0");
     if (!(p.M > 0)) return bad("M must be > 0");
     if (!(p.sigma >= 0)) return bad("sigma must be >= 0");
-    if (!isfinite(p.Gx) || !isfinite(p.Gy) || !isfinite(p.phi_ref)) return bad("non-finite input");
+    if (!isfinite(p.Gx) || !isfinite(p.Gy)) return bad("non-finite body force");
     const int64_t pitch = round_up(p.nx, TILE_X);
     if (9 * ((int64_t)p.ny * pitch + PLANE_PAD) >= (int64_t)1 << 31)
         return bad("grid too large for one instance");
@@ -159,13 +161,14 @@ void fill_inst(Instance& I, int storage, const double* phi0, const double* ux0, 
     d.mu_g = p.rho_g * p.nu_g;
     d.kappa = 1.5 * p.sigma * p.W;      // Eq. 7
     d.beta = 12.0 * p.sigma / p.W;
+    d.W = p.W;
     d.inv_w = 1.0 / p.W;
-    const double tau_f = 3.0 * p.M + 0.5;  // Eq. 14
+    const double tau_f = p.M * 3.0 + 0.5;  // Eq. 14
+    d.tau_f = tau_f;
     d.inv_tau_f = 1.0 / tau_f;
-    d.cf = 1.0 - 0.5 / tau_f;
+    d.cf = 1.0 - 1.0 / (2.0 * tau_f);
     d.Gx = p.Gx;
     d.Gy = p.Gy;
-    d.phi_ref = storage == STORE_F64 ? 0.0 : p.phi_ref;
     // bound of the initial g (equilibria at p = 0), floor for fluids at rest
     double gb = 1e-3 * std::max(p.rho_l, p.rho_g);
     const int64_t n = (int64_t)p.nx * p.ny;
@@ -174,7 +177,8 @@ void fill_inst(Instance& I, int storage, const double* phi0, const double* ux0, 
         const double u = fabs(ux0[k]) + fabs(uy0[k]);
         gb = std::max(gb, rho * (3.0 * u + 4.5 * u * u) * (4.0 / 9.0));
     }
-    const int ef = pick_exponent(p.exp_f, 0.5, storage);
+    // stored f are rest deviations, of the size of w_i phi 3 c_i.u: 0.15 covers |u| < 0.3
+    const int ef = pick_exponent(p.exp_f, 0.15, storage);
     const int eg = pick_exponent(p.exp_g, gb, storage);
     d.scale_f = ldexp(1.0, ef);
     d.inv_scale_f = ldexp(1.0, -ef);
@@ -201,7 +205,8 @@ void free_all(lbm_ctx* c) {
         if (c->g[i]) hipFree(c->g[i]);
         c->f[i] = c->g[i] = nullptr;
     }
-    void* ptrs[] = {c->q, c->q_tune, c->phiplane, c->d_insts, c->mom, c->partials, c->red_out};
+    void* ptrs[] = {c->q,       c->q_tune,    c->phiplane, c->rplane[0], c->rplane[1],
+                    c->d_insts, c->mom,       c->partials, c->red_out};
     for (void* p : ptrs)
         if (p) hipFree(p);
     for (auto& l : c->lists)
@@ -226,6 +231,8 @@ StepArgs step_args(lbm_ctx* c, int src, bool pull, int rows, bool split, void* q
     a.gdst = c->g[1 - src];
     a.q = q;
     a.phiplane = c->phiplane;
+    a.rsrc = c->rplane[src];
+    a.rdst = c->rplane[1 - src];
     a.stream = c->stream;
     return a;
 }
@@ -340,8 +347,8 @@ int autotune(lbm_ctx* c) {
         c->tile_rows = cands[0].rows;
         return LBM_OK;
     }
-    HIPCHK(c, hipMemcpyAsync(c->q_tune, c->q, c->q_elems * c->qsize, hipMemcpyDeviceToDevice,
-                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->q_tune, c->q, c->q_elems * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -412,7 +419,7 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
     c->esize = o.storage == STORE_F64 ? 8 : (o.storage == STORE_F32 ? 4 : 2);
     c->qsize = o.storage == STORE_F64 ? 8 : 4;
     c->inst.resize(n_inst);
-    int64_t off_dist = 0, off_q = 0, off_phi = 0;
+    int64_t off_dist = 0, off_q = 0, off_phi = 0, off_mp = 0;
     for (int k = 0; k < n_inst; ++k) {
         Instance& I = c->inst[k];
         I.p = p[k];
@@ -420,14 +427,17 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
         I.d.off_dist = off_dist;
         I.d.off_q = off_q;
         I.d.off_phi = off_phi;
+        I.d.off_mp = off_mp;
         off_dist += round_up(9 * I.d.plane, 64);
         off_q += round_up(2 * I.d.plane, 64);
         off_phi += round_up(I.d.plane, 64);
+        off_mp += round_up(4 * I.d.plane, 64);
         c->max_nodes = std::max(c->max_nodes, I.n_nodes);
     }
     c->dist_elems = off_dist;
     c->q_elems = off_q;
     c->phi_elems = off_phi;
+    c->mp_elems = off_mp;
 
     auto bail = [&](int rc) {
         free_all(c);
@@ -456,9 +466,11 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
         {&c->f[1], dist_bytes},
         {&c->g[0], dist_bytes},
         {&c->g[1], dist_bytes},
-        {&c->q, c->q_elems * c->qsize},
-        {&c->q_tune, c->q_elems * c->qsize},
+        {&c->q, c->q_elems * sizeof(double)},
+        {&c->q_tune, c->q_elems * sizeof(double)},
         {&c->phiplane, c->phi_elems * c->qsize},
+        {&c->rplane[0], c->mp_elems * sizeof(float)},
+        {&c->rplane[1], c->mp_elems * sizeof(float)},
         {(void**)&c->d_insts, n_inst * sizeof(InstDev)},
         {(void**)&c->mom, 5 * c->max_nodes * sizeof(double)},
         {(void**)&c->partials, 1024 * 13 * sizeof(double)},
@@ -479,6 +491,9 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
         hipMemsetAsync(c->g[i], 0, dist_bytes, c->stream);
     }
     hipMemsetAsync(c->phiplane, 0, c->phi_elems * c->qsize, c->stream);
+    hipMemsetAsync(c->q, 0, c->q_elems * sizeof(double), c->stream);
+    for (int i = 0; i < 2; ++i)
+        hipMemsetAsync(c->rplane[i], 0, c->mp_elems * sizeof(float), c->stream);
 
     std::vector<InstDev> hd(n_inst);
     for (int k = 0; k < n_inst; ++k) hd[k] = c->inst[k].d;
@@ -516,7 +531,8 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
             e = hipMemcpy(stage + 2 * n, uy0[k], n * sizeof(double), hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = launch_init(c->storage, c->d_insts, k, c->inst[k].p.nx, c->inst[k].p.ny, stage,
-                            stage + n, stage + 2 * n, c->f[0], c->g[0], c->q, c->stream);
+                            stage + n, stage + 2 * n, c->f[0], c->g[0], c->q, c->rplane[0],
+                            c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) {
             hipFree(stage);
@@ -625,8 +641,9 @@ int lbm_reduce(lbm_ctx* c, int32_t inst, const double* mask, lbm_diag* out) {
 int lbm_get_state(lbm_ctx* c, void* buf, size_t* bytes) {
     if (!c) return fail(nullptr, LBM_ERR_PARAM, "context is NULL");
     if (!bytes) return fail(c, LBM_ERR_PARAM, "bytes is NULL");
-    const uint64_t bd = c->dist_elems * c->esize, bq = c->q_elems * c->qsize;
-    const uint64_t total = sizeof(StateHeader) + 2 * bd + bq;
+    const uint64_t bd = c->dist_elems * c->esize, bq = c->q_elems * sizeof(double);
+    const uint64_t bp = c->mp_elems * sizeof(float);
+    const uint64_t total = sizeof(StateHeader) + 2 * bd + bq + bp;
     if (!buf) {
         *bytes = total;
         return LBM_OK;
@@ -642,6 +659,7 @@ int lbm_get_state(lbm_ctx* c, void* buf, size_t* bytes) {
     h.step = c->step;
     h.bytes_dist = bd;
     h.bytes_q = bq;
+    h.bytes_mp = bp;
     h.total = total;
     char* b = (char*)buf;
     memcpy(b, &h, sizeof h);
@@ -649,6 +667,7 @@ int lbm_get_state(lbm_ctx* c, void* buf, size_t* bytes) {
     HIPCHK(c, hipMemcpy(b + sizeof h, c->f[c->cur], bd, hipMemcpyDeviceToHost));
     HIPCHK(c, hipMemcpy(b + sizeof h + bd, c->g[c->cur], bd, hipMemcpyDeviceToHost));
     HIPCHK(c, hipMemcpy(b + sizeof h + 2 * bd, c->q, bq, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(b + sizeof h + 2 * bd + bq, c->rplane[c->cur], bp, hipMemcpyDeviceToHost));
     *bytes = total;
     return LBM_OK;
 }
@@ -658,17 +677,19 @@ int lbm_set_state(lbm_ctx* c, const void* buf, size_t bytes) {
     if (!buf || bytes < sizeof(StateHeader)) return fail(c, LBM_ERR_PARAM, "state buffer too small");
     StateHeader h;
     memcpy(&h, buf, sizeof h);
-    const uint64_t bd = c->dist_elems * c->esize, bq = c->q_elems * c->qsize;
+    const uint64_t bd = c->dist_elems * c->esize, bq = c->q_elems * sizeof(double);
+    const uint64_t bp = c->mp_elems * sizeof(float);
     if (h.magic != STATE_MAGIC || h.version != STATE_VERSION)
         return fail(c, LBM_ERR_PARAM, "not a state of this library");
     if (h.storage != c->storage || h.n_inst != (int32_t)c->inst.size() || h.bytes_dist != bd ||
-        h.bytes_q != bq || h.total != bytes)
+        h.bytes_q != bq || h.bytes_mp != bp || h.total != bytes)
         return fail(c, LBM_ERR_PARAM, "state does not match this context");
     const char* b = (const char*)buf;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(c->f[0], b + sizeof h, bd, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->g[0], b + sizeof h + bd, bd, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->q, b + sizeof h + 2 * bd, bq, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->rplane[0], b + sizeof h + 2 * bd + bq, bp, hipMemcpyHostToDevice));
     c->cur = 0;
     c->streamed = h.streamed != 0;
     c->step = h.step;

@@ -18,16 +18,16 @@ constexpr int NXCD = 8;         // MI355X: 8 accelerator complex dies, each with
 struct InstDev {
     int32_t nx, ny, pitch, bc_lo, bc_hi, visc_law;
     int64_t off_dist;   // offset of this instance's plane 0 in the f and g arrays
-    int64_t off_q;      // offset of its first (phi u) plane in the q array
+    int64_t off_q;      // FP64 format: offset of its two (phi u) planes in the q array
     int64_t off_phi;    // offset of its phi plane (split kernel)
+    int64_t off_mp;     // reduced formats: offset of its four planes phi_w, p_w, ux_w, uy_w
     int64_t plane;      // ny * pitch
     double rho_l, rho_g, drho;      // drho = rho_l - rho_g
     double nu_l, nu_g, inv_nu_l, inv_nu_g, mu_l, mu_g;
-    double kappa, beta, inv_w;      // k = 1.5 sigma W, beta = 12 sigma / W, 1 / W
-    double inv_tau_f, cf;           // 1 / tau_phi and 1 - 1 / (2 tau_phi)
+    double kappa, beta, W, inv_w;   // k = 1.5 sigma W, beta = 12 sigma / W, W, 1 / W
+    double tau_f, inv_tau_f, cf;    // tau_phi, 1 / tau_phi and 1 - 1 / (2 tau_phi)
     double Gx, Gy;
-    double phi_ref;                 // stored f is (f_i - w_i phi_ref) * scale_f
-    double scale_f, inv_scale_f, scale_g, inv_scale_g;
+    double scale_f, inv_scale_f, scale_g, inv_scale_g;  // storage scales 2^exp
 };
 
 // One tile of TILE_X x rows nodes of one instance.
@@ -52,7 +52,9 @@ struct StepArgs {
     void* fdst;
     void* gdst;
     void* q;
-    void* phiplane;
+    void* phiplane;     // split step: phi of the current step
+    const void* rsrc;   // reduced formats: planes phi_w, p_w, u_w of the previous step
+    void* rdst;         // and of this step
     hipStream_t stream;
 };
 
@@ -60,7 +62,7 @@ hipError_t launch_step(int storage, const StepArgs& a);
 hipError_t launch_moments(int storage, const StepArgs& a, double* out);
 hipError_t launch_init(int storage, const InstDev* insts, int inst, int nx, int ny,
                        const double* phi0, const double* ux0, const double* uy0, void* f, void* g,
-                       void* q, hipStream_t st);
+                       void* q, void* rplane, hipStream_t st);
 int reduce_blocks(int64_t n);
 hipError_t launch_reduce(const double* mom, int nx, int ny, int periodic_y, const double* mask,
                          double* partials, double* out, hipStream_t st);

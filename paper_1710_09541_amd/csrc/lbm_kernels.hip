@@ -11,6 +11,18 @@
 // other buffer.  The very first step reads the initial (already streamed) distributions
 // in place instead of pulling.
 //
+// Storage.  FP64: the populations themselves, and phi u of the previous step.  FP32 /
+// FP16 ("equilibrium deviation"): every node also writes four FP32 planes, its phi_w, p_w
+// and u_w (phi, p, u rounded to FP32).  An f slot holds (f_i - w_i phi_w) 2^exp_f and a g
+// slot (g_i - g^eq_i(rho(phi_w), p_w, u_w)) 2^exp_g, both taken at the node that wrote the
+// slot.  A reader decodes a pulled population with the planes of its source node, staged
+// with a two-node halo in LDS; the g equilibrium is evaluated by one function, identically
+// on both sides, and the g relaxation runs in FP64.  The stored numbers are thus the small
+// non-equilibrium parts, a bulk at rest is stored exactly, and the short formats round
+// small values only: slowly varying states keep their small increments (a weak body
+// force, a drifting interface) instead of losing them to the rounding of full-size
+// populations.  phi u of the previous step is phi_w u_w of the node itself.
+//
 // Boundary rules in pull form (y only; x is periodic):
 //   periodic   the source row wraps
 //   wall       half-way bounce-back: a population that would come from across the wall is
@@ -34,40 +46,85 @@ __device__ __forceinline__ C wgt(int i) {
     return i == 0 ? C(4.0 / 9.0) : (i < 5 ? C(1.0 / 9.0) : C(1.0 / 36.0));
 }
 
+// c_i . (a, b) written out per direction: with i known at compile time this folds to one
+// add or none (IEEE arithmetic may not drop a product with a zero component by itself)
+template <typename C>
+__device__ __forceinline__ C dotc(int i, C a, C b) {
+    switch (i) {
+        case 0: return C(0);
+        case 1: return a;
+        case 2: return b;
+        case 3: return -a;
+        case 4: return -b;
+        case 5: return a + b;
+        case 6: return b - a;
+        case 7: return -(a + b);
+        default: return a - b;
+    }
+}
+
+// fast reciprocal (about 1 ulp) for the FP32 arithmetic of the reduced formats
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // ------------------------------------------------------------------ storage codecs
 template <typename S>
 struct Store;
+// Element access through a 32-bit byte offset from a wave-uniform base, so the compiler can
+// address with a scalar base register plus one 32-bit vector offset.
+template <typename T>
+__device__ __forceinline__ T ld(const T* p, int o) {
+    return *(const T*)((const char*)p + (uint32_t)o * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st(T* p, int o, T v) {
+    *(T*)((char*)p + (uint32_t)o * (uint32_t)sizeof(T)) = v;
+}
+
 template <>
 struct Store<double> {
     using C = double;
-    static __device__ __forceinline__ double get(const double* p, int o) { return p[o]; }
-    static __device__ __forceinline__ void put(double* p, int o, double v) { p[o] = v; }
+    static __device__ __forceinline__ double get(const double* p, int o) { return ld(p, o); }
+    static __device__ __forceinline__ void put(double* p, int o, double v) { st(p, o, v); }
 };
 template <>
 struct Store<float> {
     using C = float;
-    static __device__ __forceinline__ float get(const float* p, int o) { return p[o]; }
-    static __device__ __forceinline__ void put(float* p, int o, float v) { p[o] = v; }
+    static __device__ __forceinline__ float get(const float* p, int o) { return ld(p, o); }
+    static __device__ __forceinline__ void put(float* p, int o, float v) { st(p, o, v); }
 };
 template <>
 struct Store<_Float16> {
     using C = float;
-    static __device__ __forceinline__ float get(const _Float16* p, int o) { return (float)p[o]; }
-    static __device__ __forceinline__ void put(_Float16* p, int o, float v) { p[o] = (_Float16)v; }
+    static __device__ __forceinline__ float get(const _Float16* p, int o) {
+        return (float)ld(p, o);
+    }
+    static __device__ __forceinline__ void put(_Float16* p, int o, float v) {
+        st(p, o, (_Float16)v);
+    }
 };
+
+// f is kept as a rest deviation in every format shorter than FP64
+template <typename S>
+constexpr bool rest_deviation() {
+    return sizeof(S) < sizeof(double);
+}
 
 // ------------------------------------------------------------------ streaming offsets
 // Element offsets (relative to the instance's plane 0) of the 9 populations arriving at
-// node (x, y).  PULL = false reads the node's own slots (the initial state is already in
-// streamed form).
+// node (x, y), and the source node (y * pitch + x) of each slot.  PULL = false reads the
+// node's own slots (the initial state is already in streamed form).
 template <bool PULL>
-__device__ __forceinline__ void pull_offsets(const InstDev& I, int x, int y, int o[9]) {
+__device__ __forceinline__ void pull_offsets(const InstDev& I, int x, int y, int o[9],
+                                             int src[9]) {
     const int pitch = I.pitch;
     const int plane = (int)I.plane;
     const int self = y * pitch + x;
     if (!PULL) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) o[i] = i * plane + self;
+        for (int i = 0; i < 9; ++i) {
+            o[i] = i * plane + self;
+            src[i] = self;
+        }
         return;
     }
     const int nx = I.nx, ny = I.ny;
@@ -79,31 +136,88 @@ __device__ __forceinline__ void pull_offsets(const InstDev& I, int x, int y, int
     const bool bl = at_lo && I.bc_lo == BC_WALL;
     const bool bh = at_hi && I.bc_hi == BC_WALL;
     const int rc = y * pitch, rm = ym * pitch, rp = yp * pitch;
+    src[0] = self;
+    src[1] = rc + xm;
+    src[3] = rc + xp;
+    src[2] = bl ? self : rm + x;
+    src[5] = bl ? self : rm + xm;
+    src[6] = bl ? self : rm + xp;
+    src[4] = bh ? self : rp + x;
+    src[7] = bh ? self : rp + xp;
+    src[8] = bh ? self : rp + xm;
     o[0] = self;
-    o[1] = plane + rc + xm;
-    o[3] = 3 * plane + rc + xp;
-    o[2] = bl ? 4 * plane + self : 2 * plane + rm + x;
-    o[5] = bl ? 7 * plane + self : 5 * plane + rm + xm;
-    o[6] = bl ? 8 * plane + self : 6 * plane + rm + xp;
-    o[4] = bh ? 2 * plane + self : 4 * plane + rp + x;
-    o[7] = bh ? 5 * plane + self : 7 * plane + rp + xp;
-    o[8] = bh ? 6 * plane + self : 8 * plane + rp + xm;
+    o[1] = plane + src[1];
+    o[3] = 3 * plane + src[3];
+    o[2] = bl ? 4 * plane + self : 2 * plane + src[2];
+    o[5] = bl ? 7 * plane + self : 5 * plane + src[5];
+    o[6] = bl ? 8 * plane + self : 6 * plane + src[6];
+    o[4] = bh ? 2 * plane + self : 4 * plane + src[4];
+    o[7] = bh ? 5 * plane + self : 7 * plane + src[7];
+    o[8] = bh ? 6 * plane + self : 8 * plane + src[8];
 }
 
-// phi of the arriving f populations at (x, y): phi_ref + sum of the stored deviations
-template <typename S, bool PULL>
-__device__ __forceinline__ typename Store<S>::C pulled_phi(const InstDev& I, const S* fb, int x,
-                                                           int y) {
-    using C = typename Store<S>::C;
-    int o[9];
-    pull_offsets<PULL>(I, x, y, o);
-    C v[9];
+// The same sources as LDS indices of a (TILE_X + 4)-wide region with a two-node halo:
+// (lx, ly) is the node's unwrapped position relative to the tile origin and gy its row.
+constexpr int RW = TILE_X + 4;
+// dir[i] is the direction of the slot that was read (the opposite one after a bounce-back).
+template <bool PULL>
+__device__ __forceinline__ void pull_local(const InstDev& I, int gy, int lx, int ly, int r[9],
+                                           int dir[9]) {
+    const int c = (ly + 2) * RW + lx + 2;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) v[i] = Store<S>::get(fb, o[i]);
+    for (int i = 0; i < 9; ++i) dir[i] = i;
+    if (!PULL) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) r[i] = c;
+        return;
+    }
+    const bool at_lo = gy == 0, at_hi = gy == I.ny - 1;
+    const bool bl = at_lo && I.bc_lo == BC_WALL, bh = at_hi && I.bc_hi == BC_WALL;
+    const int dm = (at_lo && I.bc_lo == BC_OPEN) ? 0 : RW;  // row step to upward sources
+    const int dp = (at_hi && I.bc_hi == BC_OPEN) ? 0 : RW;  // row step to downward sources
+    r[0] = c;
+    r[1] = c - 1;
+    r[3] = c + 1;
+    r[2] = bl ? c : c - dm;
+    r[5] = bl ? c : c - dm - 1;
+    r[6] = bl ? c : c - dm + 1;
+    r[4] = bh ? c : c + dp;
+    r[7] = bh ? c : c + dp + 1;
+    r[8] = bh ? c : c + dp - 1;
+    if (bl) {
+        dir[2] = 4;
+        dir[5] = 7;
+        dir[6] = 8;
+    }
+    if (bh) {
+        dir[4] = 2;
+        dir[7] = 5;
+        dir[8] = 6;
+    }
+}
+
+// phi from the 9 arriving stored values v (unscaled) and, for the rest-deviation formats,
+// the phi of their source nodes ref[] and of the node itself (base):
+//   phi = base + sum_i w_i (ref_i - base) + 2^-exp_f sum_i v_i           (Eq. 12)
+// For the rest-deviation formats *res receives the rounding error of the final addition
+// (exact, by Knuth's two-sum): phi + res is the sum before rounding to the phi format.
+template <typename C, bool REF>
+__device__ __forceinline__ C phi_of(const C (&v)[9], const C (&ref)[9], C base, C isf,
+                                    C* res = nullptr) {
     C s = v[0];
 #pragma unroll
     for (int i = 1; i < 9; ++i) s += v[i];
-    return C(I.phi_ref) + s * C(I.inv_scale_f);
+    if (!REF) return s * isf;
+    C a = wgt<C>(0) * (ref[0] - base);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) a += wgt<C>(i) * (ref[i] - base);
+    const C d = a + s * isf;
+    const C phi = base + d;
+    if (res) {
+        const C bv = phi - base;
+        *res = (base - (phi - bv)) + (d - bv);
+    }
+    return phi;
 }
 
 // row of the stencil's ghost node: wrap if periodic, else mirror the edge row
@@ -115,15 +229,137 @@ __device__ __forceinline__ int ghost_row(const InstDev& I, int y) {
 
 enum { MODE_STEP = 0, MODE_MOMENTS = 1 };
 
-// ------------------------------------------------------------------ one node
-// f: stored f deviations scaled back (f_i - w_i phi_ref), g: g_i, phi and its 8
-// neighbours, q: phi u of the previous step (updated in place).  Writes the collided
-// populations (same deviation form) into fo, go, or the moments into mom.
-template <typename C, int MODE>
-__device__ __forceinline__ void node_update(const InstDev& I, const C (&f)[9], const C (&g)[9],
-                                            C phi, C pE, C pN, C pW, C pS, C pNE, C pNW,
-                                            C pSW, C pSE, C& qx, C& qy, C (&fo)[9],
-                                            C (&go)[9], double (&mom)[5]) {
+// ------------------------------------------------------------------ FP64 node
+// The FP64 format keeps the operations and their order of the plain CPU reference
+// (sequential stencil sums, divisions by tau, rho and W, no fused multiply-add), so the two
+// round alike and agree to the last bits over long runs.
+__device__ __forceinline__ double s_exact(int i, double ux, double uy) {
+#pragma clang fp contract(off)
+    const double cu = CX[i] * ux + CY[i] * uy;
+    const double uu = ux * ux + uy * uy;
+    return wgt<double>(i) * (cu * 3.0 + cu * cu * 4.5 - uu * 1.5);   // Eq. 17
+}
+
+template <int MODE>
+__device__ __forceinline__ void node_update_f64(const InstDev& I, const double (&f)[9],
+                                                const double (&g)[9], const double (&nb)[9],
+                                                double& qx, double& qy, double (&fo)[9],
+                                                double (&go)[9], double (&mom)[5]) {
+#pragma clang fp contract(off)
+    // nb[0] = phi, nb[1..8] = phi(x + c_i); stencils of Eqs. 27-28 as sequential sums
+    const double phi = nb[0];
+    double sx = 0.0, sy = 0.0, sl = 0.0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        sx += wgt<double>(i) * CX[i] * nb[i];
+        sy += wgt<double>(i) * CY[i] * nb[i];
+        sl += 2.0 * wgt<double>(i) * (nb[i] - phi);
+    }
+    const double dpx = sx * 3.0, dpy = sy * 3.0, lap = sl * 3.0;
+    const double rho = phi * I.drho + I.rho_g;                                   // Eq. 13
+    const double mu_phi = 4.0 * I.beta * phi * (phi - 1.0) * (phi - 0.5) - I.kappa * lap;
+    const double lam = 4.0 * phi * (1.0 - phi) / I.W;                            // Eq. 3
+    const double mag = sqrt(dpx * dpx + dpy * dpy);
+    double nx_ = 0.0, ny_ = 0.0;
+    if (mag > 1e-12) {
+        nx_ = dpx / mag;
+        ny_ = dpy / mag;
+    }
+    double nu;
+    if (I.visc_law == VISC_LINEAR)
+        nu = phi * (I.nu_l - I.nu_g) + I.nu_g;
+    else if (I.visc_law == VISC_INVERSE)
+        nu = 1.0 / (phi * (I.inv_nu_l - I.inv_nu_g) + I.inv_nu_g);
+    else
+        nu = (phi >= 0.5 ? I.mu_l : I.mu_g) / rho;
+    const double tau_g = nu * 3.0 + 0.5;                                         // Eq. 23
+    const double Fx = mu_phi * dpx + I.Gx, Fy = mu_phi * dpy + I.Gy;
+    double mx = 0.0, my = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        mx += CX[i] * g[i];
+        my += CY[i] * g[i];
+    }
+    const double ux = (mx + 0.5 * Fx) / rho, uy = (my + 0.5 * Fy) / rho;       // Eq. 22a
+    double sg = 0.0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) sg += g[i];
+    const double ugp = ux * dpx + uy * dpy;
+    const double pr = 0.6 * (sg + 0.5 * I.drho * ugp + rho * s_exact(0, ux, uy));  // Eq. 22b
+    if (MODE == MODE_MOMENTS) {
+        mom[0] = phi;
+        mom[1] = rho;
+        mom[2] = pr;
+        mom[3] = ux;
+        mom[4] = uy;
+        return;
+    }
+    const double pux = phi * ux, puy = phi * uy;
+    const double dtx = pux - qx, dty = puy - qy;
+    qx = pux;
+    qy = puy;
+    const double vx = dtx * 3.0 + lam * nx_, vy = dty * 3.0 + lam * ny_;
+    const double cf = 1.0 - 1.0 / (2.0 * I.tau_f);
+    const double cg = 1.0 - 1.0 / (2.0 * tau_g);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const double w = wgt<double>(i);
+        const double cu = CX[i] * ux + CY[i] * uy;
+        const double fe = w * phi * (1.0 + cu * 3.0);                            // Eq. 9
+        const double fs = cf * w * (CX[i] * vx + CY[i] * vy);                    // Eq. 11
+        fo[i] = f[i] - (f[i] - fe) / I.tau_f + fs;                               // Eq. 8
+        const double ge = (i == 0 ? pr * 3.0 * (w - 1.0) : pr * 3.0 * w) + rho * s_exact(i, ux, uy);
+        const double cF = CX[i] * Fx + CY[i] * Fy;
+        const double cgp = CX[i] * dpx + CY[i] * dpy;
+        const double gf = cg * w * (cF * 3.0 + I.drho * cu * cgp * 3.0);         // Eq. 20
+        go[i] = g[i] - (g[i] - ge) / tau_g + gf;                                 // Eq. 15
+    }
+}
+
+// ------------------------------------------------------------------ reduced-precision node
+// FP32 reference equilibrium of the flow lattice (Eqs. 13, 16-17).  The per-node terms
+// A = rho(phi_w), B = 3 p_w (p_w / c_s^2), ux_w, uy_w and H = 1.5 |u_w|^2 are formed once,
+// then g^eq_i = w_i (B + A s_i) for i != 0, with s_i = c.u (3 + 4.5 c.u) - H, and
+// g^eq_0 = B (w_0 - 1) - A w_0 H.  The same functions, with explicit fused multiply-adds
+// and no other contraction, encode a g slot and decode it, so both agree bit for bit.
+struct RefTerms {
+    float A, B, ux, uy, H;
+};
+__device__ __forceinline__ RefTerms ref_terms(const InstDev& I, float phi, float p, float ux,
+                                              float uy) {
+#pragma clang fp contract(off)
+    RefTerms r;
+    r.A = __builtin_fmaf(phi, (float)I.drho, (float)I.rho_g);
+    r.B = p * 3.0f;
+    r.ux = ux;
+    r.uy = uy;
+    r.H = __builtin_fmaf(ux, ux, uy * uy) * 1.5f;
+    return r;
+}
+__device__ __forceinline__ float geq_ref(int i, float A, float B, float ux, float uy, float H) {
+#pragma clang fp contract(off)
+    const float w = wgt<float>(i);
+    if (i == 0) return __builtin_fmaf(B, w - 1.0f, -(A * (w * H)));
+    const float cu = dotc<float>(i, ux, uy);
+    const float s = __builtin_fmaf(cu, __builtin_fmaf(4.5f, cu, 3.0f), -H);
+    return w * __builtin_fmaf(A, s, B);
+}
+
+// f: e_i = f_i - w_i phi of the arriving populations; eg, gs: the arriving g_i as stored
+// deviation and reference equilibrium of its source node (g_i = eg_i + gs_i, summed in
+// FP64 for the moments); phi and its 8 neighbours; res: rounding error of phi (the f
+// populations sum to phi + res); qx, qy: phi_w u_w of this node at the previous step.
+// Writes the collided e_i into fo, the g deviations g*_i - g^eq_i(published moments) into
+// go and the published p_w, u_w into pw, or the moments into mom.
+template <int MODE>
+__device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&f)[9],
+                                                const float (&eg)[9], const float (&gs)[9],
+                                                float phi, float pE, float pN, float pW,
+                                                float pS, float pNE, float pNW, float pSW,
+                                                float pSE, float res, float qx, float qy,
+                                                float (&fo)[9], float (&go)[9], float (&pw)[3],
+                                                double (&mom)[5]) {
+    using C = float;
     // isotropic gradient and Laplacian (Eqs. 27-28): weights over c_s^2
     const C dpx = C(3) * (C(1.0 / 9.0) * (pE - pW) + C(1.0 / 36.0) * ((pNE - pNW) + (pSE - pSW)));
     const C dpy = C(3) * (C(1.0 / 9.0) * (pN - pS) + C(1.0 / 36.0) * ((pNE + pNW) - (pSW + pSE)));
@@ -134,10 +370,10 @@ __device__ __forceinline__ void node_update(const InstDev& I, const C (&f)[9], c
     const double rho = (double)phi * I.drho + I.rho_g;
     const C mu_phi = C(4.0 * I.beta) * phi * (phi - C(1)) * (phi - C(0.5)) - C(I.kappa) * lap;
     const C lam = C(4) * phi * (C(1) - phi) * C(I.inv_w);
-    const C mag = sqrt(dpx * dpx + dpy * dpy);
+    const C mag2 = dpx * dpx + dpy * dpy;
     C nx_ = C(0), ny_ = C(0);
-    if (mag > C(1e-12)) {
-        const C im = C(1) / mag;
+    if (mag2 > C(1e-24)) {   // |grad phi| > 1e-12
+        const C im = __builtin_amdgcn_rsqf(mag2);
         nx_ = dpx * im;
         ny_ = dpy * im;
     }
@@ -145,18 +381,18 @@ __device__ __forceinline__ void node_update(const InstDev& I, const C (&f)[9], c
     if (I.visc_law == VISC_LINEAR) {
         nu = phi * C(I.nu_l - I.nu_g) + C(I.nu_g);
     } else if (I.visc_law == VISC_INVERSE) {
-        nu = C(1) / (phi * C(I.inv_nu_l - I.inv_nu_g) + C(I.inv_nu_g));
+        nu = rcp(phi * C(I.inv_nu_l - I.inv_nu_g) + C(I.inv_nu_g));
     } else {
-        nu = (phi >= C(0.5) ? C(I.mu_l) : C(I.mu_g)) / C(rho);
+        nu = (phi >= C(0.5) ? C(I.mu_l) : C(I.mu_g)) * rcp(C(rho));
     }
-    const C inv_tau_g = C(1) / (C(3) * nu + C(0.5));   // Eq. 23
+    const C inv_tau_g = rcp(C(3) * nu + C(0.5));       // Eq. 23
     const C Fx = mu_phi * dpx + C(I.Gx);               // Eqs. 5, 19
     const C Fy = mu_phi * dpy + C(I.Gy);
 
     // moments in FP64 (Eq. 22): u first, then p
     double G[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) G[i] = (double)g[i];
+    for (int i = 0; i < 9; ++i) G[i] = (double)eg[i] + (double)gs[i];
     double jx = G[1];
     jx -= G[3];
     jx += G[5];
@@ -169,9 +405,10 @@ __device__ __forceinline__ void node_update(const InstDev& I, const C (&f)[9], c
     jy += G[6];
     jy -= G[7];
     jy -= G[8];
+    const double mx = jx + 0.5 * (double)Fx, my = jy + 0.5 * (double)Fy;   // rho u
     const double irho = 1.0 / rho;
-    const double ux = (jx + 0.5 * (double)Fx) * irho;
-    const double uy = (jy + 0.5 * (double)Fy) * irho;
+    const double ux = mx * irho;
+    const double uy = my * irho;
     double sg = G[1];
 #pragma unroll
     for (int i = 2; i < 9; ++i) sg += G[i];
@@ -188,49 +425,79 @@ __device__ __forceinline__ void node_update(const InstDev& I, const C (&f)[9], c
         return;
     }
 
-    const C cux = C(ux), cuy = C(uy), cp = C(pr), crho = C(rho), cuu = C(uu);
+    // the FP32 moments this node publishes (and encodes its g against)
+    const C cux = C(ux), cuy = C(uy), cp = C(pr);
+    pw[0] = cp;
+    pw[1] = cux;
+    pw[2] = cuy;
 
-    // d_t(phi u) as a backward difference over one step; keep phi u for the next step
-    const C pux = phi * cux, puy = phi * cuy;
-    const C Dx = pux - qx, Dy = puy - qy;
-    qx = pux;
-    qy = puy;
+    // d_t(phi u) as a backward difference over one step
+    const C Dx = phi * cux - qx, Dy = phi * cuy - qy;
 
-    // f collision (Eqs. 8, 9, 11) in deviation form: d_i = f_i - w_i phi_ref
+    // f collision (Eqs. 8, 9, 11) on e_i = f_i - w_i phi.  The populations sum to phi + res
+    // before and after the collision (sum f^eq = phi, sum F_i = 0); the rest population is
+    // taken from that invariant, so neither the rounding of phi nor the inexact FP32 weights
+    // can bias the total phi.
     const C itf = C(I.inv_tau_f), cf = C(I.cf);
-    const C phid = phi - C(I.phi_ref);
     const C ax = C(3) * Dx + lam * nx_;
     const C ay = C(3) * Dy + lam * ny_;
+    const C phi3 = C(3) * phi;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 1; i < 9; ++i) {
         const C w = wgt<C>(i);
-        const C cu = C(CX[i]) * cux + C(CY[i]) * cuy;
-        const C feq = w * phid + C(3) * w * phi * cu;
-        const C src = cf * w * (C(CX[i]) * ax + C(CY[i]) * ay);
+        const C feq = w * phi3 * dotc<C>(i, cux, cuy);
+        const C src = cf * w * dotc<C>(i, ax, ay);
         fo[i] = f[i] - (f[i] - feq) * itf + src;
     }
+    C t = fo[1];
+#pragma unroll
+    for (int i = 2; i < 9; ++i) t += fo[i];
+    fo[0] = res - t;
 
-    // g collision (Eqs. 15-17, 20)
+    // g collision (Eqs. 15-17, 20) on deviations from the published equilibrium gw:
+    // g*_i - gw_i = (1 - 1/tau_g)(g_i - gw_i) + G_i + (1/tau_g)(g^eq_i - gw_i).  Of the last
+    // term, which only reflects the FP32 rounding of the published moments, the part that
+    // carries momentum is kept exactly (a 3 w_i c_i.dj correction with dj = rho u -
+    // sum_i c_i gw_i formed in FP64), so the collision conserves momentum to FP32 rounding of
+    // small deviations and a weak body force is not lost to rounding.
+    const RefTerms R = ref_terms(I, phi, cp, cux, cuy);
+    float gw[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) gw[i] = geq_ref(i, R.A, R.B, cux, cuy, R.H);
+    double wx = (double)gw[1];
+    wx -= (double)gw[3];
+    wx += (double)gw[5];
+    wx -= (double)gw[6];
+    wx -= (double)gw[7];
+    wx += (double)gw[8];
+    double wy = (double)gw[2];
+    wy -= (double)gw[4];
+    wy += (double)gw[5];
+    wy += (double)gw[6];
+    wy -= (double)gw[7];
+    wy -= (double)gw[8];
+    const C cjx = C(3) * inv_tau_g * C(mx - wx), cjy = C(3) * inv_tau_g * C(my - wy);
     const C cg = C(1) - C(0.5) * inv_tau_g;
-    const C drho = C(I.drho);
+    const C keep = C(1) - inv_tau_g;
+    const C drho3 = C(3) * C(I.drho);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const C w = wgt<C>(i);
-        const C cu = C(CX[i]) * cux + C(CY[i]) * cuy;
-        const C s = w * (C(3) * cu + C(4.5) * cu * cu - C(1.5) * cuu);
-        const C geq = (i == 0 ? C(-5.0 / 3.0) * cp : C(3) * w * cp) + crho * s;
-        const C cF = C(CX[i]) * Fx + C(CY[i]) * Fy;
-        const C cgp = C(CX[i]) * dpx + C(CY[i]) * dpy;
-        const C frc = cg * w * (C(3) * cF + C(3) * drho * cu * cgp);
-        go[i] = g[i] - (g[i] - geq) * inv_tau_g + frc;
+        const C frc = cg * w *
+                      (C(3) * dotc<C>(i, Fx, Fy) +
+                       drho3 * dotc<C>(i, cux, cuy) * dotc<C>(i, dpx, dpy));
+        const C d = eg[i] + (gs[i] - gw[i]);
+        go[i] = keep * d + frc + w * dotc<C>(i, cjx, cjy);
     }
 }
 
 // ------------------------------------------------------------------ fused step kernel
 // One block of 256 threads (64 x 4) owns a tile of 64 x 4K nodes.  Each thread pulls the
-// f, g and q of its K nodes, writes their phi into an LDS tile, the block recomputes phi
-// on the one-node halo ring from pulled f (neighbouring tiles' data, mostly L2 hits), and
-// after one barrier every node has its 3 x 3 phi neighbourhood in LDS.
+// f and g of its K nodes and puts their phi into an LDS tile; the block recomputes phi on
+// the one-node halo ring from pulled f (neighbouring tiles' data, mostly L2 hits), and
+// after a barrier every node has its 3 x 3 phi neighbourhood in LDS.  In the reduced
+// formats the block first stages the previous step's four planes (phi_w, p_w, u_w) over
+// the tile plus two nodes into LDS, to decode the pulled populations.
 //
 // Block b runs tile (b % 8) * per_xcd + b / 8: the hardware deals blocks round-robin to
 // the 8 XCDs, so each XCD walks one contiguous run of tiles and finds the halo rows of
@@ -238,26 +505,33 @@ __device__ __forceinline__ void node_update(const InstDev& I, const C (&f)[9], c
 //
 // RING_FROM_PLANE (split step): the halo ring is read from a phi plane written by
 // k_phi_plane instead of being recomputed.
+//
+// q: FP64 format, phi u of the previous step (2 planes, updated in place).
+// msrc / mdst: reduced formats, the planes phi_w, p_w, ux_w, uy_w of the previous step
+// (read) and of this step (written).
 template <typename S, int K, bool PULL, int MODE, bool RING_FROM_PLANE>
-__global__ __launch_bounds__(BLOCK) void k_step(const InstDev* __restrict__ insts,
-                                                const TileDesc* __restrict__ tiles, int ntiles,
-                                                int per_xcd, const S* __restrict__ fsrc,
-                                                const S* __restrict__ gsrc, S* __restrict__ fdst,
-                                                S* __restrict__ gdst,
-                                                typename Store<S>::C* __restrict__ q,
-                                                const typename Store<S>::C* __restrict__ phiplane,
-                                                double* __restrict__ mom_out) {
+__global__ __launch_bounds__(BLOCK) void k_step(
+    const InstDev* __restrict__ insts, const TileDesc* __restrict__ tiles, int ntiles,
+    int per_xcd, const S* __restrict__ fsrc, const S* __restrict__ gsrc, S* __restrict__ fdst,
+    S* __restrict__ gdst, double* __restrict__ q,
+    const typename Store<S>::C* __restrict__ phiplane, const float* __restrict__ msrc,
+    float* __restrict__ mdst, double* __restrict__ mom_out) {
     using C = typename Store<S>::C;
+    constexpr bool REF = rest_deviation<S>();
     constexpr int TY = 4 * K;
     constexpr int LW = TILE_X + 2;
+    constexpr int NR = REF ? (TY + 4) * RW : 1;
     __shared__ C sphi[(TY + 2) * LW];
+    // previous step's per-node terms with a two-node halo: (A, B, ux, uy) and (phi_w, H)
+    __shared__ float4 sq[NR];
+    __shared__ float2 sw[NR];
 
     const int b = blockIdx.x;
     const int t = (b % NXCD) * per_xcd + b / NXCD;
     if (t >= ntiles) return;
     const TileDesc T = tiles[t];
     const InstDev& I = insts[T.inst];
-    const int nx = I.nx, ny = I.ny;
+    const int nx = I.nx, ny = I.ny, pitch = I.pitch;
     const int w = min(TILE_X, nx - T.x0);
     const int h = min(TY, ny - T.y0);
     const int tid = threadIdx.x;
@@ -267,11 +541,44 @@ __global__ __launch_bounds__(BLOCK) void k_step(const InstDev* __restrict__ inst
 
     const S* fb = fsrc + I.off_dist;
     const S* gb = gsrc + I.off_dist;
-    C* qb = q + I.off_q;
     const int plane = (int)I.plane;
     const C isf = C(I.inv_scale_f), isg = C(I.inv_scale_g);
 
-    C f[K][9], g[K][9], qx[K], qy[K];
+    // previous planes over the tile and a two-node halo (wrapped; clamped rows beyond a
+    // wall or an open side are never sources)
+    if (REF) {
+        const float* mb = msrc + I.off_mp;
+        const bool pery = I.bc_lo == BC_PERIODIC;
+        // one wrap suffices when the grid is at least as wide / tall as the staged block
+        const bool wide = nx >= RW, tall = ny >= TY + 4;
+        for (int idx = tid; idx < NR; idx += BLOCK) {
+            const int sy = idx / RW - 2, sx = idx - (idx / RW) * RW - 2;
+            int gx = T.x0 + sx;
+            if (wide) {
+                gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
+            } else {
+                gx %= nx;
+                gx = gx < 0 ? gx + nx : gx;
+            }
+            int gy = T.y0 + sy;
+            if (!pery) {
+                gy = min(max(gy, 0), ny - 1);
+            } else if (tall) {
+                gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+            } else {
+                gy %= ny;
+                gy = gy < 0 ? gy + ny : gy;
+            }
+            const int o = gy * pitch + gx;
+            const float ph = ld(mb, o);
+            const RefTerms R =
+                ref_terms(I, ph, ld(mb, plane + o), ld(mb, 2 * plane + o), ld(mb, 3 * plane + o));
+            sq[idx] = make_float4(R.A, R.B, R.ux, R.uy);
+            sw[idx] = make_float2(ph, R.H);
+        }
+    }
+
+    C f[K][9], g[K][9];
     bool valid[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -279,25 +586,32 @@ __global__ __launch_bounds__(BLOCK) void k_step(const InstDev* __restrict__ inst
         valid[k] = lx < w && yl < h;
         if (valid[k]) {
             const int y = T.y0 + yl;
-            int o[9];
-            pull_offsets<PULL>(I, x, y, o);
+            int o[9], src[9];
+            pull_offsets<PULL>(I, x, y, o, src);
 #pragma unroll
             for (int i = 0; i < 9; ++i) f[k][i] = Store<S>::get(fb, o[i]);
 #pragma unroll
             for (int i = 0; i < 9; ++i) g[k][i] = Store<S>::get(gb, o[i]);
-            const int self = y * I.pitch + x;
-            qx[k] = qb[self];
-            qy[k] = qb[plane + self];
         }
     }
-    // phi of the tile's own nodes (Eq. 12)
+    if (REF) __syncthreads();
+
+    // phi of the tile's own nodes (and, reduced formats, its rounding residual)
+    C res[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
+        res[k] = C(0);
         if (valid[k]) {
-            C s = f[k][0];
+            const int yl = ly + 4 * k;
+            C ref[9], base = C(0);
+            if (REF) {
+                int r[9], dir[9];
+                pull_local<PULL>(I, T.y0 + yl, lx, yl, r, dir);
 #pragma unroll
-            for (int i = 1; i < 9; ++i) s += f[k][i];
-            sphi[(ly + 4 * k + 1) * LW + lx + 1] = C(I.phi_ref) + s * isf;
+                for (int i = 0; i < 9; ++i) ref[i] = sw[r[i]].x;
+                base = sw[(yl + 2) * RW + lx + 2].x;
+            }
+            sphi[(yl + 1) * LW + lx + 1] = phi_of<C, REF>(f[k], ref, base, isf, &res[k]);
         }
     }
     // halo ring: top row, bottom row (w + 2 each), left and right columns (h each)
@@ -319,12 +633,30 @@ __global__ __launch_bounds__(BLOCK) void k_step(const InstDev* __restrict__ inst
         }
         int gx = T.x0 + rx;
         gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
-        const int gy = ghost_row(I, T.y0 + ry);
+        const int yraw = T.y0 + ry;
+        const int gy = ghost_row(I, yraw);
         C v;
         if (RING_FROM_PLANE) {
-            v = phiplane[I.off_phi + gy * I.pitch + gx];
+            v = phiplane[I.off_phi + gy * pitch + gx];
         } else {
-            v = pulled_phi<S, PULL>(I, fb, gx, gy);
+            int o[9], src[9];
+            pull_offsets<PULL>(I, gx, gy, o, src);
+            C fv[9], ref[9], base = C(0);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fv[i] = Store<S>::get(fb, o[i]);
+            if (REF) {
+                // a mirrored ghost row is the edge row itself; a wrapped one keeps its
+                // unwrapped position (the staged halo holds the wrapped values)
+                const bool mirrored = (yraw < 0 && I.bc_lo != BC_PERIODIC) ||
+                                      (yraw >= ny && I.bc_hi != BC_PERIODIC);
+                const int lyl = mirrored ? gy - T.y0 : ry;
+                int r[9], dir[9];
+                pull_local<PULL>(I, gy, rx, lyl, r, dir);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) ref[i] = sw[r[i]].x;
+                base = sw[(lyl + 2) * RW + rx + 2].x;
+            }
+            v = phi_of<C, REF>(fv, ref, base, isf);
         }
         sphi[(ry + 1) * LW + rx + 1] = v;
     }
@@ -341,40 +673,70 @@ __global__ __launch_bounds__(BLOCK) void k_step(const InstDev* __restrict__ inst
         const C* r0 = sphi + yl * LW + lx;        // row below (y - 1)
         const C* r1 = r0 + LW;                    // own row
         const C* r2 = r1 + LW;                    // row above (y + 1)
-        C fd[9], gd[9], fo[9], go[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            fd[i] = f[k][i] * isf;
-            gd[i] = g[k][i] * isg;
-        }
+        const C phi = r1[1];
+        const int self = y * pitch + x;
         double mom[5];
-        node_update<C, MODE>(I, fd, gd, r1[1], r1[2], r2[1], r1[0], r0[1], r2[2], r2[0], r0[0],
-                             r0[2], qx[k], qy[k], fo, go, mom);
-        const int self = y * I.pitch + x;
+        if constexpr (REF) {
+            int r[9], dir[9];
+            pull_local<PULL>(I, y, lx, yl, r, dir);
+            float fd[9], eg[9], gs[9], fo[9], go[9], pw[3];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const float4 q4 = sq[r[i]];
+                const float2 q2 = sw[r[i]];
+                fd[i] = __builtin_fmaf(wgt<float>(i), q2.x - phi, f[k][i] * isf);
+                eg[i] = g[k][i] * isg;
+                gs[i] = geq_ref(dir[i], q4.x, q4.y, q4.z, q4.w, q2.y);
+            }
+            const int me = (yl + 2) * RW + lx + 2;
+            const float qx = sw[me].x * sq[me].z, qy = sw[me].x * sq[me].w;
+            node_update_ref<MODE>(I, fd, eg, gs, phi, r1[2], r2[1], r1[0], r0[1], r2[2], r2[0],
+                                  r0[0], r0[2], res[k], qx, qy, fo, go, pw, mom);
+            if (MODE == MODE_STEP) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) Store<S>::put(fo_b, i * plane + self, fo[i] * sf);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) Store<S>::put(go_b, i * plane + self, go[i] * sgs);
+                float* mo = mdst + I.off_mp;
+                st(mo, self, phi);
+                st(mo, plane + self, pw[0]);
+                st(mo, 2 * plane + self, pw[1]);
+                st(mo, 3 * plane + self, pw[2]);
+            }
+        } else {
+            double* qb = q + I.off_q;
+            double qx = qb[self], qy = qb[plane + self];
+            const double nb[9] = {phi, r1[2], r2[1], r1[0], r0[1], r2[2], r2[0], r0[0], r0[2]};
+            double fo[9], go[9];
+            node_update_f64<MODE>(I, f[k], g[k], nb, qx, qy, fo, go, mom);
+            if (MODE == MODE_STEP) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) Store<S>::put(fo_b, i * plane + self, fo[i]);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) Store<S>::put(go_b, i * plane + self, go[i]);
+                qb[self] = qx;
+                qb[plane + self] = qy;
+            }
+        }
         if (MODE == MODE_MOMENTS) {
             const int64_t n = (int64_t)nx * ny;
             const int64_t c = (int64_t)y * nx + x;
 #pragma unroll
             for (int m = 0; m < 5; ++m) mom_out[m * n + c] = mom[m];
-        } else {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) Store<S>::put(fo_b, i * plane + self, fo[i] * sf);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) Store<S>::put(go_b, i * plane + self, go[i] * sgs);
-            qb[self] = qx[k];
-            qb[plane + self] = qy[k];
         }
     }
 }
 
 // ------------------------------------------------------------------ split step: phi plane
-// First half of the two-launch step: phi (Eq. 12) of every node from the pulled f.
+// First half of the two-launch step: phi (Eq. 12) of every node from the pulled f, with the
+// same arithmetic as the fused kernel (source-node phi read from memory, not LDS).
 template <typename S, int K>
-__global__ __launch_bounds__(BLOCK) void k_phi_plane(const InstDev* __restrict__ insts,
-                                                     const TileDesc* __restrict__ tiles,
-                                                     int ntiles, int per_xcd,
-                                                     const S* __restrict__ fsrc,
-                                                     typename Store<S>::C* __restrict__ phiplane) {
+__global__ __launch_bounds__(BLOCK) void k_phi_plane(
+    const InstDev* __restrict__ insts, const TileDesc* __restrict__ tiles, int ntiles,
+    int per_xcd, const S* __restrict__ fsrc, const float* __restrict__ msrc,
+    typename Store<S>::C* __restrict__ phiplane) {
+    using C = typename Store<S>::C;
+    constexpr bool REF = rest_deviation<S>();
     const int b = blockIdx.x;
     const int t = (b % NXCD) * per_xcd + b / NXCD;
     if (t >= ntiles) return;
@@ -385,209 +747,89 @@ __global__ __launch_bounds__(BLOCK) void k_phi_plane(const InstDev* __restrict__
     const int lx = threadIdx.x & (TILE_X - 1);
     const int ly = threadIdx.x >> 6;
     const S* fb = fsrc + I.off_dist;
+    const float* rb = REF ? msrc + I.off_mp : nullptr;   // phi_w plane
+    const C isf = C(I.inv_scale_f);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int yl = ly + 4 * k;
         if (lx < w && yl < h) {
             const int x = T.x0 + lx, y = T.y0 + yl;
-            phiplane[I.off_phi + y * I.pitch + x] = pulled_phi<S, true>(I, fb, x, y);
+            int o[9], src[9];
+            pull_offsets<true>(I, x, y, o, src);
+            C v[9], ref[9], base = C(0);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) v[i] = Store<S>::get(fb, o[i]);
+            if (REF) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) ref[i] = rb[src[i]];
+                base = rb[y * I.pitch + x];
+            }
+            phiplane[I.off_phi + y * I.pitch + x] = phi_of<C, REF>(v, ref, base, isf);
         }
     }
 }
 
 // ------------------------------------------------------------------ initial state
-// f = f^eq(phi0, u0) (Eq. 9), g = g^eq(p = 0, u0) with rho(phi0) (Eq. 16), q = phi0 u0, in
-// the storage codec, already in streamed form.
+__device__ __forceinline__ double init_feq(double w, double ph, double cu) {
+#pragma clang fp contract(off)
+    return w * ph * (1.0 + cu * 3.0);
+}
+__device__ __forceinline__ double init_rho(double ph, double drho, double rho_g) {
+#pragma clang fp contract(off)
+    return ph * drho + rho_g;
+}
+
+// f = f^eq(phi0, u0) (Eq. 9), g = g^eq(p = 0, u0) with rho(phi0) (Eq. 16), phi u = phi0 u0,
+// in the storage format, already in streamed form (FP64: q planes; reduced formats: the
+// planes phi_w, p_w = 0, u_w and deviations from them).
 template <typename S>
 __global__ __launch_bounds__(BLOCK) void k_init(const InstDev* __restrict__ insts, int inst,
                                                 const double* __restrict__ phi0,
                                                 const double* __restrict__ ux0,
                                                 const double* __restrict__ uy0,
                                                 S* __restrict__ f, S* __restrict__ g,
-                                                typename Store<S>::C* __restrict__ q) {
+                                                double* __restrict__ q, float* __restrict__ mp) {
     using C = typename Store<S>::C;
+    constexpr bool REF = rest_deviation<S>();
     const InstDev& I = insts[inst];
     const int x = blockIdx.x * TILE_X + (threadIdx.x & (TILE_X - 1));
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= I.nx || y >= I.ny) return;
     const int c = y * I.nx + x;
     const double ph = phi0[c], ux = ux0[c], uy = uy0[c];
-    const double rho = ph * I.drho + I.rho_g;
-    const double uu = ux * ux + uy * uy;
+    const double rho = init_rho(ph, I.drho, I.rho_g);
     const int self = y * I.pitch + x;
     const int plane = (int)I.plane;
     S* fb = f + I.off_dist;
     S* gb = g + I.off_dist;
+    const float phw = (float)ph, uxw = (float)ux, uyw = (float)uy;
+    const RefTerms R = ref_terms(I, phw, 0.0f, uxw, uyw);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const double w = wgt<double>(i);
         const double cu = CX[i] * ux + CY[i] * uy;
-        const double feq = w * ph * (1.0 + 3.0 * cu);
-        const double s = w * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-        const double geq = rho * s;   // p = 0
-        Store<S>::put(fb, i * plane + self, (C)((feq - w * I.phi_ref) * I.scale_f));
-        Store<S>::put(gb, i * plane + self, (C)(geq * I.scale_g));
-    }
-    C* qb = q + I.off_q;
-    qb[self] = (C)(ph * ux);
-    qb[plane + self] = (C)(ph * uy);
-}
-
-// ------------------------------------------------------------------ reductions
-// Per-block partials over the FP64 moment planes of one instance, then one block folds
-// the partials in a fixed order: the result does not depend on timing.
-constexpr int NRED = 13;
-enum {
-    R_SPHI, R_SRHO, R_KIN, R_MAXU2, R_MINRHO, R_MINPHI, R_MAXPHI, R_PIN_S, R_PIN_N, R_POUT_S,
-    R_POUT_N, R_CROSS, R_NONFIN
-};
-
-__device__ __forceinline__ void red_init(double (&a)[NRED]) {
-#pragma unroll
-    for (int k = 0; k < NRED; ++k) a[k] = 0.0;
-    a[R_MINRHO] = INFINITY;
-    a[R_MINPHI] = INFINITY;
-    a[R_MAXPHI] = -INFINITY;
-}
-
-__device__ __forceinline__ void red_join(double (&a)[NRED], const double* b) {
-    a[R_SPHI] += b[R_SPHI];
-    a[R_SRHO] += b[R_SRHO];
-    a[R_KIN] += b[R_KIN];
-    a[R_MAXU2] = fmax(a[R_MAXU2], b[R_MAXU2]);
-    a[R_MINRHO] = fmin(a[R_MINRHO], b[R_MINRHO]);
-    a[R_MINPHI] = fmin(a[R_MINPHI], b[R_MINPHI]);
-    a[R_MAXPHI] = fmax(a[R_MAXPHI], b[R_MAXPHI]);
-    a[R_PIN_S] += b[R_PIN_S];
-    a[R_PIN_N] += b[R_PIN_N];
-    a[R_POUT_S] += b[R_POUT_S];
-    a[R_POUT_N] += b[R_POUT_N];
-    a[R_CROSS] += b[R_CROSS];
-    a[R_NONFIN] += b[R_NONFIN];
-}
-
-// fixed-shape tree over the block's 256 slots in LDS
-__device__ __forceinline__ void block_fold(double (&acc)[NRED], double* sh) {
-    const int tid = threadIdx.x;
-#pragma unroll
-    for (int k = 0; k < NRED; ++k) sh[k * BLOCK + tid] = acc[k];
-    __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-        if (tid < s) {
-            double other[NRED];
-#pragma unroll
-            for (int k = 0; k < NRED; ++k) other[k] = sh[k * BLOCK + tid + s];
-            red_join(acc, other);
-#pragma unroll
-            for (int k = 0; k < NRED; ++k) sh[k * BLOCK + tid] = acc[k];
-        }
-        __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(BLOCK) void k_reduce_partial(const double* __restrict__ mom, int nx,
-                                                          int ny, int periodic_y, double xc,
-                                                          double yc, double r_in, double r_out,
-                                                          double* __restrict__ partials) {
-    __shared__ double sh[NRED * BLOCK];
-    double acc[NRED];
-    red_init(acc);
-    const int64_t n = (int64_t)nx * ny;
-    const double* phi = mom;
-    const double* rho = mom + n;
-    const double* p = mom + 2 * n;
-    const double* ux = mom + 3 * n;
-    const double* uy = mom + 4 * n;
-    for (int64_t c = (int64_t)blockIdx.x * BLOCK + threadIdx.x; c < n;
-         c += (int64_t)gridDim.x * BLOCK) {
-        const int y = (int)(c / nx), x = (int)(c - (int64_t)y * nx);
-        const double ph = phi[c], r = rho[c], pr = p[c], u = ux[c], v = uy[c];
-        const bool fin = isfinite(ph) && isfinite(r) && isfinite(pr) && isfinite(u) && isfinite(v);
-        if (!fin) {
-            acc[R_NONFIN] += 1.0;
-            continue;
-        }
-        const double u2 = u * u + v * v;
-        acc[R_SPHI] += ph;
-        acc[R_SRHO] += r;
-        acc[R_KIN] += 0.5 * r * u2;
-        acc[R_MAXU2] = fmax(acc[R_MAXU2], u2);
-        acc[R_MINRHO] = fmin(acc[R_MINRHO], r);
-        acc[R_MINPHI] = fmin(acc[R_MINPHI], ph);
-        acc[R_MAXPHI] = fmax(acc[R_MAXPHI], ph);
-        double dx = fabs(x + 0.5 - xc);
-        dx = fmin(dx, nx - dx);
-        double dy = fabs(y + 0.5 - yc);
-        if (periodic_y) dy = fmin(dy, ny - dy);
-        const double d = sqrt(dx * dx + dy * dy);
-        if (d < r_in) {
-            acc[R_PIN_S] += pr;
-            acc[R_PIN_N] += 1.0;
-        }
-        if (d > r_out) {
-            acc[R_POUT_S] += pr;
-            acc[R_POUT_N] += 1.0;
-        }
-        // crossings of phi = 0.5 with the right neighbour (periodic) and the upper one
-        const bool liq = ph >= 0.5;
-        const int xr = x + 1 == nx ? 0 : x + 1;
-        if ((phi[(int64_t)y * nx + xr] >= 0.5) != liq) acc[R_CROSS] += 1.0;
-        if (y + 1 < ny || periodic_y) {
-            const int yu = y + 1 == ny ? 0 : y + 1;
-            if ((phi[(int64_t)yu * nx + x] >= 0.5) != liq) acc[R_CROSS] += 1.0;
+        const double fe = init_feq(w, ph, cu);
+        const double ge = rho * s_exact(i, ux, uy);   // p = 0
+        if (REF) {
+            const double ed = fe - w * (double)phw;
+            const double eg = ge - (double)geq_ref(i, R.A, R.B, uxw, uyw, R.H);
+            Store<S>::put(fb, i * plane + self, (float)ed * (float)I.scale_f);
+            Store<S>::put(gb, i * plane + self, (float)eg * (float)I.scale_g);
+        } else {
+            Store<S>::put(fb, i * plane + self, (C)fe);
+            Store<S>::put(gb, i * plane + self, (C)ge);
         }
     }
-    block_fold(acc, sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NRED; ++k) partials[(int64_t)blockIdx.x * NRED + k] = acc[k];
-    }
-}
-
-// out = {sum_phi, sum_rho, kinetic, max_u, min_rho, min_phi, max_phi, p_in, p_out,
-//        crossings, spread_radius, nonfinite}
-__global__ __launch_bounds__(BLOCK) void k_reduce_final(const double* __restrict__ partials,
-                                                        int nblocks,
-                                                        const double* __restrict__ mom, int nx,
-                                                        int ny, double xc, int y_row,
-                                                        double* __restrict__ out) {
-    __shared__ double sh[NRED * BLOCK];
-    double acc[NRED];
-    red_init(acc);
-    for (int b = threadIdx.x; b < nblocks; b += BLOCK) red_join(acc, partials + (int64_t)b * NRED);
-    block_fold(acc, sh);
-    // spreading radius on row y_row (interpolated crossings between x and x + 1)
-    __shared__ double rmax[BLOCK];
-    double best = 0.0;
-    if (y_row >= 0 && y_row < ny) {
-        const double* row = mom + (int64_t)y_row * nx;
-        for (int x = threadIdx.x; x < nx - 1; x += BLOCK) {
-            const double a = row[x] - 0.5, b = row[x + 1] - 0.5;
-            if ((a >= 0.0) != (b >= 0.0)) {
-                const double xs = x + 0.5 + a / (a - b);
-                best = fmax(best, fabs(xs - xc));
-            }
-        }
-    }
-    rmax[threadIdx.x] = best;
-    __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) rmax[threadIdx.x] = fmax(rmax[threadIdx.x], rmax[threadIdx.x + s]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        out[0] = acc[R_SPHI];
-        out[1] = acc[R_SRHO];
-        out[2] = acc[R_KIN];
-        out[3] = sqrt(acc[R_MAXU2]);
-        out[4] = acc[R_MINRHO];
-        out[5] = acc[R_MINPHI];
-        out[6] = acc[R_MAXPHI];
-        out[7] = acc[R_PIN_N] > 0 ? acc[R_PIN_S] / acc[R_PIN_N] : 0.0;
-        out[8] = acc[R_POUT_N] > 0 ? acc[R_POUT_S] / acc[R_POUT_N] : 0.0;
-        out[9] = acc[R_CROSS];
-        out[10] = rmax[0];
-        out[11] = acc[R_NONFIN];
+    if (REF) {
+        float* mb = mp + I.off_mp;
+        mb[self] = phw;
+        mb[plane + self] = 0.0f;
+        mb[2 * plane + self] = uxw;
+        mb[3 * plane + self] = uyw;
+    } else {
+        double* qb = q + I.off_q;
+        qb[self] = ph * ux;
+        qb[plane + self] = ph * uy;
     }
 }
 
@@ -607,18 +849,21 @@ hipError_t step_k(const StepArgs& a) {
     const S* gs = (const S*)a.gsrc;
     S* fd = (S*)a.fdst;
     S* gd = (S*)a.gdst;
-    C* q = (C*)a.q;
+    double* q = (double*)a.q;
     C* ph = (C*)a.phiplane;
+    const float* rs = (const float*)a.rsrc;
+    float* rd = (float*)a.rdst;
     if (!a.pull) {
         k_step<S, K, false, MODE_STEP, false><<<grid, BLOCK, 0, a.stream>>>(
-            a.insts, a.tiles, a.ntiles, per, fs, gs, fd, gd, q, ph, nullptr);
+            a.insts, a.tiles, a.ntiles, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
     } else if (a.split) {
-        k_phi_plane<S, K><<<grid, BLOCK, 0, a.stream>>>(a.insts, a.tiles, a.ntiles, per, fs, ph);
+        k_phi_plane<S, K><<<grid, BLOCK, 0, a.stream>>>(a.insts, a.tiles, a.ntiles, per, fs, rs,
+                                                        ph);
         k_step<S, K, true, MODE_STEP, true><<<grid, BLOCK, 0, a.stream>>>(
-            a.insts, a.tiles, a.ntiles, per, fs, gs, fd, gd, q, ph, nullptr);
+            a.insts, a.tiles, a.ntiles, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
     } else {
         k_step<S, K, true, MODE_STEP, false><<<grid, BLOCK, 0, a.stream>>>(
-            a.insts, a.tiles, a.ntiles, per, fs, gs, fd, gd, q, ph, nullptr);
+            a.insts, a.tiles, a.ntiles, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
     }
     return hipGetLastError();
 }
@@ -638,24 +883,28 @@ hipError_t moments_s(const StepArgs& a, double* out) {
     using C = typename Store<S>::C;
     int per;
     const int grid = grid_for(a.ntiles, per);
+    const S* fs = (const S*)a.fsrc;
+    const S* gs = (const S*)a.gsrc;
+    const float* rs = (const float*)a.rsrc;
     if (a.pull)
         k_step<S, 1, true, MODE_MOMENTS, false><<<grid, BLOCK, 0, a.stream>>>(
-            a.insts, a.tiles, a.ntiles, per, (const S*)a.fsrc, (const S*)a.gsrc, nullptr, nullptr,
-            (C*)a.q, nullptr, out);
+            a.insts, a.tiles, a.ntiles, per, fs, gs, nullptr, nullptr, (double*)a.q, nullptr,
+            rs, nullptr, out);
     else
         k_step<S, 1, false, MODE_MOMENTS, false><<<grid, BLOCK, 0, a.stream>>>(
-            a.insts, a.tiles, a.ntiles, per, (const S*)a.fsrc, (const S*)a.gsrc, nullptr, nullptr,
-            (C*)a.q, nullptr, out);
+            a.insts, a.tiles, a.ntiles, per, fs, gs, nullptr, nullptr, (double*)a.q, nullptr,
+            rs, nullptr, out);
     return hipGetLastError();
 }
 
 template <typename S>
 hipError_t init_s(const InstDev* insts, int inst, int nx, int ny, const double* phi0,
-                  const double* ux0, const double* uy0, void* f, void* g, void* q,
+                  const double* ux0, const double* uy0, void* f, void* g, void* q, void* rplane,
                   hipStream_t st) {
     using C = typename Store<S>::C;
     dim3 grid((nx + TILE_X - 1) / TILE_X, (ny + 3) / 4);
-    k_init<S><<<grid, BLOCK, 0, st>>>(insts, inst, phi0, ux0, uy0, (S*)f, (S*)g, (C*)q);
+    k_init<S><<<grid, BLOCK, 0, st>>>(insts, inst, phi0, ux0, uy0, (S*)f, (S*)g, (double*)q,
+                                      (float*)rplane);
     return hipGetLastError();
 }
 }  // namespace
@@ -680,30 +929,16 @@ hipError_t launch_moments(int storage, const StepArgs& a, double* out) {
 
 hipError_t launch_init(int storage, const InstDev* insts, int inst, int nx, int ny,
                        const double* phi0, const double* ux0, const double* uy0, void* f, void* g,
-                       void* q, hipStream_t st) {
+                       void* q, void* rplane, hipStream_t st) {
     switch (storage) {
-        case STORE_F64: return init_s<double>(insts, inst, nx, ny, phi0, ux0, uy0, f, g, q, st);
-        case STORE_F32: return init_s<float>(insts, inst, nx, ny, phi0, ux0, uy0, f, g, q, st);
-        case STORE_F16: return init_s<_Float16>(insts, inst, nx, ny, phi0, ux0, uy0, f, g, q, st);
+        case STORE_F64:
+            return init_s<double>(insts, inst, nx, ny, phi0, ux0, uy0, f, g, q, rplane, st);
+        case STORE_F32:
+            return init_s<float>(insts, inst, nx, ny, phi0, ux0, uy0, f, g, q, rplane, st);
+        case STORE_F16:
+            return init_s<_Float16>(insts, inst, nx, ny, phi0, ux0, uy0, f, g, q, rplane, st);
         default: return hipErrorInvalidValue;
     }
-}
-
-int reduce_blocks(int64_t n) {
-    int64_t b = (n + BLOCK - 1) / BLOCK;
-    return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
-}
-
-hipError_t launch_reduce(const double* mom, int nx, int ny, int periodic_y, const double* mask,
-                         double* partials, double* out, hipStream_t st) {
-    const int nb = reduce_blocks((int64_t)nx * ny);
-    k_reduce_partial<<<nb, BLOCK, 0, st>>>(mom, nx, ny, periodic_y, mask[0], mask[1], mask[2],
-                                           mask[3], partials);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_reduce_final<<<1, BLOCK, 0, st>>>(partials, nb, mom, nx, ny, mask[0],
-                                        mask[4] < 0 ? -1 : (int)mask[4], out);
-    return hipGetLastError();
 }
 
 }  // namespace lbm

@@ -34,7 +34,7 @@ class lbm_params(C.Structure):
                 ("rho_l", C.c_double), ("rho_g", C.c_double),
                 ("nu_l", C.c_double), ("nu_g", C.c_double),
                 ("sigma", C.c_double), ("W", C.c_double), ("M", C.c_double),
-                ("Gx", C.c_double), ("Gy", C.c_double), ("phi_ref", C.c_double),
+                ("Gx", C.c_double), ("Gy", C.c_double),
                 ("exp_f", C.c_int32), ("exp_g", C.c_int32)]
 
 
@@ -68,6 +68,13 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("liblbm_hip.so is not built; run `python -m paper_1710_09541_amd.build`")
+    # PyTorch ships its own HIP runtime under the same soname; loading it first makes the
+    # library and torch share one runtime, so torch streams and device pointers are valid
+    # arguments.  (Loaded the other way round, the process would hold two runtimes.)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     P, D = C.POINTER, C.POINTER(C.c_double)
     L.lbm_init.argtypes = [P(lbm_params), C.c_int32, P(lbm_options), P(D), P(D), P(D),
@@ -97,14 +104,13 @@ def _dptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def make_params(case, phi_ref=0.0, exp_f=LBM_EXP_AUTO, exp_g=LBM_EXP_AUTO) -> lbm_params:
+def make_params(case, exp_f=LBM_EXP_AUTO, exp_g=LBM_EXP_AUTO) -> lbm_params:
     p = lbm_params()
     p.nx, p.ny = int(case["nx"]), int(case["ny"])
     p.bc_ylo, p.bc_yhi = int(case["bc_ylo"]), int(case["bc_yhi"])
     p.visc_law = int(case["visc_law"])
     for k in ("rho_l", "rho_g", "nu_l", "nu_g", "sigma", "W", "M", "Gx", "Gy"):
         setattr(p, k, float(case[k]))
-    p.phi_ref = float(case.get("phi_ref", phi_ref))
     p.exp_f, p.exp_g = int(exp_f), int(exp_g)
     return p
 
@@ -193,10 +199,10 @@ class Simulation:
     """One library context over one or more cases (dicts from ``cases``)."""
 
     def __init__(self, case_or_cases, storage="f32", kernel="auto", tile_rows=0,
-                 use_graph=True, check_every=0, stream=None, phi_ref=0.0):
+                 use_graph=True, check_every=0, stream=None):
         cs = case_or_cases if isinstance(case_or_cases, (list, tuple)) else [case_or_cases]
         self.cases = list(cs)
-        params = [make_params(c, phi_ref=phi_ref) for c in self.cases]
+        params = [make_params(c) for c in self.cases]
         opts = make_options(storage, kernel, tile_rows, use_graph, check_every)
         self.ctx = lbm_init(params, opts, [c["phi0"] for c in self.cases],
                             [c["ux0"] for c in self.cases], [c["uy0"] for c in self.cases],
