@@ -80,8 +80,9 @@ typedef struct {
     double W;                 /* interface width, > 0 (Eqs. 3, 7) */
     double M;                 /* mobility, > 0; tau_phi = M / c_s^2 + 0.5 (Eq. 14) */
     double Gx, Gy;            /* body-force density (Eq. 4b) */
-    int32_t exp_f, exp_g;     /* F16/F32 storage exponents, or LBM_EXP_AUTO (F16: from the
-                                 initial fields; F32: 0); ignored for F64 */
+    int32_t exp_f, exp_g;     /* F16 storage exponents (stored value = deviation * 2^exp), or
+                                 LBM_EXP_AUTO to derive them from the initial fields;
+                                 ignored for F32 and F64 */
 } lbm_params;
 
 /* Context-wide options. */

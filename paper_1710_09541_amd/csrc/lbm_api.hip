@@ -132,8 +132,8 @@ std::string check_params(const lbm_params& p, int k) {
 }
 
 int pick_exponent(int given, double bound, int storage) {
+    if (storage != STORE_F16) return 0;   // only the 16-bit format is scaled
     if (given != LBM_EXP_AUTO) return given;
-    if (storage != STORE_F16) return 0;
     // keep 32x head-room below the largest half (65504)
     int e = (int)floor(log2(65504.0 / (32.0 * bound)));
     return std::max(-8, std::min(24, e));

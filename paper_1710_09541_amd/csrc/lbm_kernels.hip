@@ -113,7 +113,8 @@ constexpr bool rest_deviation() {
 // Element offsets (relative to the instance's plane 0) of the 9 populations arriving at
 // node (x, y), and the source node (y * pitch + x) of each slot.  PULL = false reads the
 // node's own slots (the initial state is already in streamed form).
-template <bool PULL>
+// INTERIOR: the node and its neighbours are away from every edge (no wrap, no boundary).
+template <bool PULL, bool INTERIOR = false>
 __device__ __forceinline__ void pull_offsets(const InstDev& I, int x, int y, int o[9],
                                              int src[9]) {
     const int pitch = I.pitch;
@@ -124,6 +125,14 @@ __device__ __forceinline__ void pull_offsets(const InstDev& I, int x, int y, int
         for (int i = 0; i < 9; ++i) {
             o[i] = i * plane + self;
             src[i] = self;
+        }
+        return;
+    }
+    if (INTERIOR) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            src[i] = self - dotc<int>(i, 1, pitch);
+            o[i] = i * plane + src[i];
         }
         return;
     }
@@ -160,7 +169,7 @@ __device__ __forceinline__ void pull_offsets(const InstDev& I, int x, int y, int
 // (lx, ly) is the node's unwrapped position relative to the tile origin and gy its row.
 constexpr int RW = TILE_X + 4;
 // dir[i] is the direction of the slot that was read (the opposite one after a bounce-back).
-template <bool PULL>
+template <bool PULL, bool INTERIOR = false>
 __device__ __forceinline__ void pull_local(const InstDev& I, int gy, int lx, int ly, int r[9],
                                            int dir[9]) {
     const int c = (ly + 2) * RW + lx + 2;
@@ -169,6 +178,11 @@ __device__ __forceinline__ void pull_local(const InstDev& I, int gy, int lx, int
     if (!PULL) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) r[i] = c;
+        return;
+    }
+    if (INTERIOR) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) r[i] = c - dotc<int>(i, 1, RW);
         return;
     }
     const bool at_lo = gy == 0, at_hi = gy == I.ny - 1;
@@ -509,31 +523,22 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
 // q: FP64 format, phi u of the previous step (2 planes, updated in place).
 // msrc / mdst: reduced formats, the planes phi_w, p_w, ux_w, uy_w of the previous step
 // (read) and of this step (written).
-template <typename S, int K, bool PULL, int MODE, bool RING_FROM_PLANE>
-__global__ __launch_bounds__(BLOCK) void k_step(
-    const InstDev* __restrict__ insts, const TileDesc* __restrict__ tiles, int ntiles,
-    int per_xcd, const S* __restrict__ fsrc, const S* __restrict__ gsrc, S* __restrict__ fdst,
-    S* __restrict__ gdst, double* __restrict__ q,
-    const typename Store<S>::C* __restrict__ phiplane, const float* __restrict__ msrc,
-    float* __restrict__ mdst, double* __restrict__ mom_out) {
+template <typename S, int K, bool PULL, int MODE, bool RING_FROM_PLANE, bool INTERIOR>
+__device__ __forceinline__ void step_tile(
+    const InstDev& I, const TileDesc& T, const S* __restrict__ fsrc,
+    const S* __restrict__ gsrc, S* __restrict__ fdst, S* __restrict__ gdst,
+    double* __restrict__ q, const typename Store<S>::C* __restrict__ phiplane,
+    const float* __restrict__ msrc, float* __restrict__ mdst, double* __restrict__ mom_out,
+    typename Store<S>::C* sphi, float4* sq, float2* sw) {
     using C = typename Store<S>::C;
     constexpr bool REF = rest_deviation<S>();
+    constexpr bool SCALED = sizeof(S) < sizeof(float);   // only the 16-bit format is scaled
     constexpr int TY = 4 * K;
     constexpr int LW = TILE_X + 2;
     constexpr int NR = REF ? (TY + 4) * RW : 1;
-    __shared__ C sphi[(TY + 2) * LW];
-    // previous step's per-node terms with a two-node halo: (A, B, ux, uy) and (phi_w, H)
-    __shared__ float4 sq[NR];
-    __shared__ float2 sw[NR];
-
-    const int b = blockIdx.x;
-    const int t = (b % NXCD) * per_xcd + b / NXCD;
-    if (t >= ntiles) return;
-    const TileDesc T = tiles[t];
-    const InstDev& I = insts[T.inst];
     const int nx = I.nx, ny = I.ny, pitch = I.pitch;
-    const int w = min(TILE_X, nx - T.x0);
-    const int h = min(TY, ny - T.y0);
+    const int w = INTERIOR ? TILE_X : min(TILE_X, nx - T.x0);
+    const int h = INTERIOR ? TY : min(TY, ny - T.y0);
     const int tid = threadIdx.x;
     const int lx = tid & (TILE_X - 1);
     const int ly = tid >> 6;
@@ -542,7 +547,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(
     const S* fb = fsrc + I.off_dist;
     const S* gb = gsrc + I.off_dist;
     const int plane = (int)I.plane;
-    const C isf = C(I.inv_scale_f), isg = C(I.inv_scale_g);
+    const C isf = SCALED ? C(I.inv_scale_f) : C(1), isg = SCALED ? C(I.inv_scale_g) : C(1);
 
     // previous planes over the tile and a two-node halo (wrapped; clamped rows beyond a
     // wall or an open side are never sources)
@@ -554,14 +559,16 @@ __global__ __launch_bounds__(BLOCK) void k_step(
         for (int idx = tid; idx < NR; idx += BLOCK) {
             const int sy = idx / RW - 2, sx = idx - (idx / RW) * RW - 2;
             int gx = T.x0 + sx;
-            if (wide) {
+            if (INTERIOR) {
+            } else if (wide) {
                 gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
             } else {
                 gx %= nx;
                 gx = gx < 0 ? gx + nx : gx;
             }
             int gy = T.y0 + sy;
-            if (!pery) {
+            if (INTERIOR) {
+            } else if (!pery) {
                 gy = min(max(gy, 0), ny - 1);
             } else if (tall) {
                 gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
@@ -587,7 +594,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(
         if (valid[k]) {
             const int y = T.y0 + yl;
             int o[9], src[9];
-            pull_offsets<PULL>(I, x, y, o, src);
+            pull_offsets<PULL, INTERIOR>(I, x, y, o, src);
 #pragma unroll
             for (int i = 0; i < 9; ++i) f[k][i] = Store<S>::get(fb, o[i]);
 #pragma unroll
@@ -606,7 +613,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(
             C ref[9], base = C(0);
             if (REF) {
                 int r[9], dir[9];
-                pull_local<PULL>(I, T.y0 + yl, lx, yl, r, dir);
+                pull_local<PULL, INTERIOR>(I, T.y0 + yl, lx, yl, r, dir);
 #pragma unroll
                 for (int i = 0; i < 9; ++i) ref[i] = sw[r[i]].x;
                 base = sw[(yl + 2) * RW + lx + 2].x;
@@ -632,15 +639,15 @@ __global__ __launch_bounds__(BLOCK) void k_step(
             ry = tid - 2 * (w + 2) - h;
         }
         int gx = T.x0 + rx;
-        gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
+        if (!INTERIOR) gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
         const int yraw = T.y0 + ry;
-        const int gy = ghost_row(I, yraw);
+        const int gy = INTERIOR ? yraw : ghost_row(I, yraw);
         C v;
         if (RING_FROM_PLANE) {
             v = phiplane[I.off_phi + gy * pitch + gx];
         } else {
             int o[9], src[9];
-            pull_offsets<PULL>(I, gx, gy, o, src);
+            pull_offsets<PULL, INTERIOR>(I, gx, gy, o, src);
             C fv[9], ref[9], base = C(0);
 #pragma unroll
             for (int i = 0; i < 9; ++i) fv[i] = Store<S>::get(fb, o[i]);
@@ -651,7 +658,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(
                                       (yraw >= ny && I.bc_hi != BC_PERIODIC);
                 const int lyl = mirrored ? gy - T.y0 : ry;
                 int r[9], dir[9];
-                pull_local<PULL>(I, gy, rx, lyl, r, dir);
+                pull_local<PULL, INTERIOR>(I, gy, rx, lyl, r, dir);
 #pragma unroll
                 for (int i = 0; i < 9; ++i) ref[i] = sw[r[i]].x;
                 base = sw[(lyl + 2) * RW + rx + 2].x;
@@ -664,7 +671,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(
 
     S* fo_b = fdst + I.off_dist;
     S* go_b = gdst + I.off_dist;
-    const C sf = C(I.scale_f), sgs = C(I.scale_g);
+    const C sf = SCALED ? C(I.scale_f) : C(1), sgs = SCALED ? C(I.scale_g) : C(1);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if (!valid[k]) continue;
@@ -678,7 +685,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(
         double mom[5];
         if constexpr (REF) {
             int r[9], dir[9];
-            pull_local<PULL>(I, y, lx, yl, r, dir);
+            pull_local<PULL, INTERIOR>(I, y, lx, yl, r, dir);
             float fd[9], eg[9], gs[9], fo[9], go[9], pw[3];
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
@@ -725,6 +732,41 @@ __global__ __launch_bounds__(BLOCK) void k_step(
             for (int m = 0; m < 5; ++m) mom_out[m * n + c] = mom[m];
         }
     }
+}
+
+
+// A tile whose staged region (two nodes around it) lies inside the grid runs a copy of the
+// body without wrap and boundary logic; edge tiles take the general path.
+template <typename S, int K, bool PULL, int MODE, bool RING_FROM_PLANE>
+__global__ __launch_bounds__(BLOCK) void k_step(
+    const InstDev* __restrict__ insts, const TileDesc* __restrict__ tiles, int ntiles,
+    int per_xcd, const S* __restrict__ fsrc, const S* __restrict__ gsrc, S* __restrict__ fdst,
+    S* __restrict__ gdst, double* __restrict__ q,
+    const typename Store<S>::C* __restrict__ phiplane, const float* __restrict__ msrc,
+    float* __restrict__ mdst, double* __restrict__ mom_out) {
+    using C = typename Store<S>::C;
+    constexpr int TY = 4 * K;
+    constexpr int NR = rest_deviation<S>() ? (TY + 4) * RW : 1;
+    __shared__ C sphi[(TY + 2) * (TILE_X + 2)];
+    // previous step's per-node terms with a two-node halo: (A, B, ux, uy) and (phi_w, H)
+    __shared__ float4 sq[NR];
+    __shared__ float2 sw[NR];
+
+    const int b = blockIdx.x;
+    const int t = (b % NXCD) * per_xcd + b / NXCD;
+    if (t >= ntiles) return;
+    const TileDesc T = tiles[t];
+    const InstDev& I = insts[T.inst];
+    const bool interior = PULL && T.x0 >= 2 && T.x0 + TILE_X + 2 <= I.nx && T.y0 >= 2 &&
+                          T.y0 + TY + 2 <= I.ny;
+    if (interior)
+        step_tile<S, K, PULL, MODE, RING_FROM_PLANE, true>(I, T, fsrc, gsrc, fdst, gdst, q,
+                                                           phiplane, msrc, mdst, mom_out, sphi,
+                                                           sq, sw);
+    else
+        step_tile<S, K, PULL, MODE, RING_FROM_PLANE, false>(I, T, fsrc, gsrc, fdst, gdst, q,
+                                                            phiplane, msrc, mdst, mom_out, sphi,
+                                                            sq, sw);
 }
 
 // ------------------------------------------------------------------ split step: phi plane

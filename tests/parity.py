@@ -35,6 +35,19 @@ def errors(case, got, ref):
     return e
 
 
+def sensitivity(case, steps, eps=1e-7, seed=5):
+    """Errors of the oracle against itself when phi0 is perturbed by relative noise of size
+    eps (about the rounding of a 32-bit store).  Where the interface normal is taken at a
+    point of vanishing gradient (the centre of a symmetric drop, the midpoint between
+    periodic images) the direction of n = grad phi / |grad phi| is set by rounding, so a
+    result can be no closer to the oracle than this spread."""
+    rng = np.random.default_rng(seed)
+    phi = case["phi0"] * (1.0 + eps * rng.standard_normal(case["phi0"].shape))
+    s = OracleSim(case, phi, case["ux0"], case["uy0"])
+    s.step(steps)
+    return errors(case, s.moments(), run_oracle(case, steps))
+
+
 def report(name, storage, e):
     print("[parity] %-28s %-4s phi %.2e  u %.2e  p %.2e  rho %.2e  (tol %.0e)"
           % (name, storage, e["phi"], e["u"], e["p"], e["rho"], TOL[storage]), flush=True)
