@@ -24,7 +24,8 @@
  *   S4  u from Eq. 22a
  *   S5  p from Eq. 22b (u first, then p)
  *   S6  D = phi u - Q (backward difference for d_t(phi u) in Eq. 11); Q <- phi u
- *   S7  collide f: BGK + source F_i                        (Eqs. 8, 9, 11)
+ *   S7  collide f: BGK + source F_i                        (Eqs. 8, 9, 11); with the local
+ *       scheme of Eq. 29 the normal in F_i comes from the non-equilibrium first moment
  *   S8  collide g: BGK + forcing G_i                       (Eqs. 15-17, 20)
  *   S9  stream, with periodic / half-way bounce-back / zero-gradient open boundaries.
  * Readings where the paper is silent are listed next to the code that takes them.
@@ -50,12 +51,15 @@ static const double INV_CS2 = 3.0;
 
 enum { ORC_PERIODIC = 0, ORC_WALL = 1, ORC_OPEN = 2 };
 enum { ORC_NU_LINEAR = 0, ORC_NU_INVERSE = 1, ORC_MU_STEP = 2 };
+enum { ORC_GRAD_ISOTROPIC = 0, ORC_GRAD_LOCAL_NEQ = 1 };
 
 typedef struct {
     int32_t nx, ny;
     int32_t bc_ylo, bc_yhi;  /* ORC_PERIODIC on both sides or on neither */
     int32_t visc_law;        /* ORC_NU_LINEAR (Eq. 24), ORC_NU_INVERSE (Eq. 25), ORC_MU_STEP (Eq. 26) */
-    int32_t reserved;
+    int32_t grad_scheme;     /* normal n in F_i: ORC_GRAD_ISOTROPIC (Eq. 2 with Eq. 27) or
+                                ORC_GRAD_LOCAL_NEQ (Eq. 29); everything else always uses
+                                Eqs. 27-28 */
     double rho_l, rho_g;     /* phase densities (Eq. 13) */
     double nu_l, nu_g;       /* phase kinematic viscosities */
     double sigma, W, M;      /* surface tension, interface width, mobility */
@@ -170,6 +174,38 @@ static void stencil_node(const orc_params* p, const double* phi, int x, int y, d
     *lap = sl * INV_CS2;
 }
 
+/* Normal vector from the local non-equilibrium scheme (Sec. 2.3, Eq. 29).  With
+ * A = -c_s^2 tau_f, B = M lambda (dt = 1) and
+ *     C = sum_i c_i (f_i - f_i^eq) + 0.5 d_t(phi u)
+ * (the time derivative in C is the one of Eq. 11: it is what the Chapman-Enskog expansion
+ * of Eq. 8 leaves in the first moment of f - f^eq, C = (A + B/|grad phi|) grad phi),
+ * Eq. 29a gives |grad phi| = (|C| + B)/(c_s^2 tau_f) and then A + B/|grad phi| =
+ * -c_s^2 tau_f |C| / (|C| + B) < 0, so Eq. 29b followed by n = grad phi / |grad phi|
+ * (Eq. 2) is exactly
+ *     n = -C / |C|.
+ * That closed form is evaluated here: the printed two-step form divides 0 by 0 where
+ * C = 0 (every node of an equilibrium state) and cancels badly where |C| << B.  Where
+ * |C| does not exceed 1e-12 the direction is undefined and n is taken as zero, as for the
+ * isotropic scheme. */
+static void normal_local_neq(const double f[9], const double fe[9], double dtx, double dty,
+                             double* nx_, double* ny_) {
+    double cx = 0.0, cy = 0.0;
+    for (int i = 0; i < 9; ++i) {
+        cx += CX[i] * (f[i] - fe[i]);
+        cy += CY[i] * (f[i] - fe[i]);
+    }
+    cx += 0.5 * dtx;
+    cy += 0.5 * dty;
+    double cmag = sqrt(cx * cx + cy * cy);
+    if (cmag > 1e-12) {
+        *nx_ = -cx / cmag;
+        *ny_ = -cy / cmag;
+    } else {
+        *nx_ = 0.0;
+        *ny_ = 0.0;
+    }
+}
+
 /* --------------------------------------------------------------- node closure */
 
 typedef struct {
@@ -261,6 +297,8 @@ static void step_once(orc_sim* s) {
             /* S7: f_i* = f_i - (f_i - f_i^eq)/tau_f + F_i  (Eq. 8) */
             double fe[9], fs[9], fpost[9];
             feq_node(o.phi, o.ux, o.uy, fe);
+            if (p->grad_scheme == ORC_GRAD_LOCAL_NEQ)                        /* Eq. 29 */
+                normal_local_neq(f, fe, dtx, dty, &o.nx, &o.ny);
             fsource_node(s->tau_f, dtx, dty, o.lambda, o.nx, o.ny, fs);
             for (int i = 0; i < 9; ++i) fpost[i] = f[i] - (f[i] - fe[i]) / s->tau_f + fs[i];
 
@@ -327,6 +365,7 @@ int orc_check(const orc_params* p) {
     if ((p->bc_ylo == ORC_PERIODIC) != (p->bc_yhi == ORC_PERIODIC)) return -2;
     if (p->bc_ylo < 0 || p->bc_ylo > 2 || p->bc_yhi < 0 || p->bc_yhi > 2) return -3;
     if (p->visc_law < 0 || p->visc_law > 2) return -4;
+    if (p->grad_scheme < 0 || p->grad_scheme > 1) return -7;
     if (!(p->rho_l > 0) || !(p->rho_g > 0) || !(p->nu_l > 0) || !(p->nu_g > 0)) return -5;
     if (!(p->W > 0) || !(p->M > 0) || !(p->sigma >= 0)) return -6;
     return 0;
@@ -474,4 +513,12 @@ void orc_closure(const orc_params* p, double phi, double dpx, double dpy, double
     closure_node(&s, phi, dpx, dpy, lap, g, &o);
     double v[11] = {o.rho, o.mu_phi, o.lambda, o.nx, o.ny, o.tau_g, o.Fx, o.Fy, o.ux, o.uy, o.p};
     memcpy(out, v, sizeof(v));
+}
+
+/* Eq. 29 normal at one node from its f_i, phi, u and d_t(phi u); out = {n_x, n_y}. */
+void orc_normal_local_neq(const double* f, double phi, double ux, double uy, double dtx,
+                          double dty, double* out) {
+    double fe[9];
+    feq_node(phi, ux, uy, fe);
+    normal_local_neq(f, fe, dtx, dty, &out[0], &out[1]);
 }

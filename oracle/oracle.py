@@ -12,12 +12,13 @@ from . import build as _build
 
 PERIODIC, WALL, OPEN = 0, 1, 2
 NU_LINEAR, NU_INVERSE, MU_STEP = 0, 1, 2
+GRAD_ISOTROPIC, GRAD_LOCAL_NEQ = 0, 1
 
 
 class OrcParams(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32),
                 ("bc_ylo", C.c_int32), ("bc_yhi", C.c_int32),
-                ("visc_law", C.c_int32), ("reserved", C.c_int32),
+                ("visc_law", C.c_int32), ("grad_scheme", C.c_int32),
                 ("rho_l", C.c_double), ("rho_g", C.c_double),
                 ("nu_l", C.c_double), ("nu_g", C.c_double),
                 ("sigma", C.c_double), ("W", C.c_double), ("M", C.c_double),
@@ -53,6 +54,7 @@ def lib():
         L.orc_gforce.argtypes = [C.c_double] * 8 + [_D]
         L.orc_stencil.argtypes = [P, _D, _D, _D, _D]
         L.orc_closure.argtypes = [P] + [C.c_double] * 4 + [_D, _D]
+        L.orc_normal_local_neq.argtypes = [_D] + [C.c_double] * 5 + [_D]
         _lib = L
     return _lib
 
@@ -63,6 +65,7 @@ def make_params(case) -> OrcParams:
     p.nx, p.ny = int(case["nx"]), int(case["ny"])
     p.bc_ylo, p.bc_yhi = int(case["bc_ylo"]), int(case["bc_yhi"])
     p.visc_law = int(case["visc_law"])
+    p.grad_scheme = int(case.get("grad_scheme", GRAD_ISOTROPIC))
     for k in ("rho_l", "rho_g", "nu_l", "nu_g", "sigma", "W", "M", "Gx", "Gy"):
         setattr(p, k, float(case[k]))
     return p
@@ -171,3 +174,11 @@ def closure(case, phi, dpx, dpy, lap, g):
     lib().orc_closure(C.byref(make_params(case)), phi, dpx, dpy, lap,
                       np.ascontiguousarray(g, dtype=np.float64), out)
     return dict(zip(CLOSURE_KEYS, out))
+
+
+def normal_local_neq(f, phi, ux, uy, dtx, dty):
+    """Eq. 29 normal at one node; returns (n_x, n_y)."""
+    out = np.empty(2)
+    lib().orc_normal_local_neq(np.ascontiguousarray(f, dtype=np.float64), phi, ux, uy, dtx,
+                               dty, out)
+    return out

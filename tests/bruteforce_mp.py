@@ -89,6 +89,24 @@ def node_update(prm, P, x, y, grid, f, g, q):
           WA * phi * (1 - 3 * ux), WA * phi * (1 - 3 * uy),
           WD * phi * (1 + 3 * (ux + uy)), WD * phi * (1 + 3 * (-ux + uy)),
           WD * phi * (1 + 3 * (-ux - uy)), WD * phi * (1 + 3 * (ux - uy))]
+    if prm.get("grad_scheme", 0) == 1:
+        # Eq. 29 in its printed two-step form: |grad phi| from Eq. 29a, then grad phi from
+        # Eq. 29b, then n = grad phi / |grad phi|; C is the first moment of f - f^eq plus
+        # half the time derivative of phi u.  Where C vanishes the direction is undefined
+        # and n is zero.
+        Cx = ((f[1] - fe[1]) - (f[3] - fe[3]) + (f[5] - fe[5]) - (f[6] - fe[6])
+              - (f[7] - fe[7]) + (f[8] - fe[8]) + HALF * Dx)
+        Cy = ((f[2] - fe[2]) - (f[4] - fe[4]) + (f[5] - fe[5]) + (f[6] - fe[6])
+              - (f[7] - fe[7]) - (f[8] - fe[8]) + HALF * Dy)
+        Cm = mp.sqrt(Cx * Cx + Cy * Cy)
+        if Cm > mp.mpf("1e-12"):
+            A = -tau_f / 3
+            B = M * lam
+            gm = (-Cm - B) / A
+            den = A + B / gm
+            nx_, ny_ = (Cx / den) / gm, (Cy / den) / gm
+        else:
+            nx_, ny_ = mp.mpf(0), mp.mpf(0)
     ax = 3 * Dx + lam * nx_
     ay = 3 * Dy + lam * ny_
     cf = 1 - 1 / (2 * tau_f)
