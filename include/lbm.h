@@ -52,6 +52,14 @@ enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1, LBM_BC_OPEN = 2 };
  * dynamic viscosity (mu_l for phi >= 0.5, else mu_g) with nu = mu / rho(phi) */
 enum { LBM_VISC_LINEAR = 0, LBM_VISC_INVERSE = 1, LBM_VISC_STEP_MU = 2 };
 
+/* interface normal n in the phase-field source F_i (Eq. 11).  ISOTROPIC: n = grad phi /
+ * |grad phi| from the isotropic stencil of Eq. 27 (Eq. 2).  LOCAL_NEQ: the local
+ * non-equilibrium scheme of Eq. 29, which reduces exactly to n = -C / |C| with
+ * C = sum_i c_i (f_i - f_i^eq) + d_t(phi u) / 2.  Either way n = 0 where the magnitude
+ * (|grad phi| or |C|) does not exceed 1e-12.  The chemical potential, the force and the
+ * moments always use Eqs. 27-28. */
+enum { LBM_GRAD_ISOTROPIC = 0, LBM_GRAD_LOCAL_NEQ = 1 };
+
 /* storage of the distributions.  F64: doubles, FP64 arithmetic.  F32 / F16: float / IEEE
  * half holding rest deviations (f_i - w_i phi_w) 2^exp_f, phi_w the order parameter of the
  * node that wrote the slot (kept in an FP32 phi plane), and g_i 2^exp_g; arithmetic in
@@ -73,7 +81,7 @@ typedef struct {
     int32_t nx, ny;           /* lattice size, each >= 3 */
     int32_t bc_ylo, bc_yhi;   /* LBM_BC_*; PERIODIC must be set on both sides or on neither */
     int32_t visc_law;         /* LBM_VISC_* */
-    int32_t reserved0;
+    int32_t grad_scheme;      /* LBM_GRAD_* */
     double rho_l, rho_g;      /* phase densities, > 0 (Eq. 13) */
     double nu_l, nu_g;        /* phase kinematic viscosities, > 0 */
     double sigma;             /* surface tension, >= 0 (Eq. 7) */

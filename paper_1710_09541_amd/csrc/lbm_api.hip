@@ -119,6 +119,7 @@ std::string check_params(const lbm_params& p, int k) {
     if ((p.bc_ylo == LBM_BC_PERIODIC) != (p.bc_yhi == LBM_BC_PERIODIC))
         return bad("periodic must be set on both y sides or on neither");
     if (p.visc_law < 0 || p.visc_law > 2) return bad("unknown viscosity law");
+    if (p.grad_scheme < 0 || p.grad_scheme > 1) return bad("unknown gradient scheme");
     if (!(p.rho_l > 0) || !(p.rho_g > 0)) return bad("densities must be > 0");
     if (!(p.nu_l > 0) || !(p.nu_g > 0)) return bad("viscosities must be > 0");
     if (!(p.W > 0)) return bad("W must be > 0");
@@ -149,6 +150,7 @@ void fill_inst(Instance& I, int storage, const double* phi0, const double* ux0, 
     d.bc_lo = p.bc_ylo;
     d.bc_hi = p.bc_yhi;
     d.visc_law = p.visc_law;
+    d.grad_scheme = p.grad_scheme;
     d.plane = (int64_t)p.ny * d.pitch + PLANE_PAD;
     d.rho_l = p.rho_l;
     d.rho_g = p.rho_g;

@@ -8,6 +8,7 @@ namespace lbm {
 
 enum { BC_PERIODIC = 0, BC_WALL = 1, BC_OPEN = 2 };
 enum { VISC_LINEAR = 0, VISC_INVERSE = 1, VISC_STEP_MU = 2 };
+enum { GRAD_ISOTROPIC = 0, GRAD_LOCAL_NEQ = 1 };
 enum { STORE_F64 = 0, STORE_F32 = 1, STORE_F16 = 2 };
 
 constexpr int TILE_X = 64;      // tile width = one wavefront of 64 lanes
@@ -16,7 +17,7 @@ constexpr int NXCD = 8;         // MI355X: 8 accelerator complex dies, each with
 
 // Per-instance constants, read with uniform (scalar) loads.  Distances are in elements.
 struct InstDev {
-    int32_t nx, ny, pitch, bc_lo, bc_hi, visc_law;
+    int32_t nx, ny, pitch, bc_lo, bc_hi, visc_law, grad_scheme;
     int64_t off_dist;   // offset of this instance's plane 0 in the f and g arrays
     int64_t off_q;      // FP64 format: offset of its two (phi u) planes in the q array
     int64_t off_phi;    // offset of its phi plane (split kernel)

@@ -312,6 +312,37 @@ __device__ __forceinline__ void node_update_f64(const InstDev& I, const double (
     const double dtx = pux - qx, dty = puy - qy;
     qx = pux;
     qy = puy;
+    double fe[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const double cu = CX[i] * ux + CY[i] * uy;
+        fe[i] = wgt<double>(i) * phi * (1.0 + cu * 3.0);                         // Eq. 9
+    }
+    if (I.grad_scheme == GRAD_LOCAL_NEQ) {
+        // Eq. 29: n = -C/|C|, C = sum_i c_i (f_i - f_i^eq) + d_t(phi u)/2, the sums taken
+        // over i in increasing order
+        double cx = f[1] - fe[1];
+        cx -= f[3] - fe[3];
+        cx += f[5] - fe[5];
+        cx -= f[6] - fe[6];
+        cx -= f[7] - fe[7];
+        cx += f[8] - fe[8];
+        double cy = f[2] - fe[2];
+        cy -= f[4] - fe[4];
+        cy += f[5] - fe[5];
+        cy += f[6] - fe[6];
+        cy -= f[7] - fe[7];
+        cy -= f[8] - fe[8];
+        cx += 0.5 * dtx;
+        cy += 0.5 * dty;
+        const double cm = sqrt(cx * cx + cy * cy);
+        nx_ = 0.0;
+        ny_ = 0.0;
+        if (cm > 1e-12) {
+            nx_ = -cx / cm;
+            ny_ = -cy / cm;
+        }
+    }
     const double vx = dtx * 3.0 + lam * nx_, vy = dty * 3.0 + lam * ny_;
     const double cf = 1.0 - 1.0 / (2.0 * I.tau_f);
     const double cg = 1.0 - 1.0 / (2.0 * tau_g);
@@ -319,9 +350,8 @@ __device__ __forceinline__ void node_update_f64(const InstDev& I, const double (
     for (int i = 0; i < 9; ++i) {
         const double w = wgt<double>(i);
         const double cu = CX[i] * ux + CY[i] * uy;
-        const double fe = w * phi * (1.0 + cu * 3.0);                            // Eq. 9
         const double fs = cf * w * (CX[i] * vx + CY[i] * vy);                    // Eq. 11
-        fo[i] = f[i] - (f[i] - fe) / I.tau_f + fs;                               // Eq. 8
+        fo[i] = f[i] - (f[i] - fe[i]) / I.tau_f + fs;                            // Eq. 8
         const double ge = (i == 0 ? pr * 3.0 * (w - 1.0) : pr * 3.0 * w) + rho * s_exact(i, ux, uy);
         const double cF = CX[i] * Fx + CY[i] * Fy;
         const double cgp = CX[i] * dpx + CY[i] * dpy;
@@ -364,8 +394,9 @@ __device__ __forceinline__ float geq_ref(int i, float A, float B, float ux, floa
 // FP64 for the moments); phi and its 8 neighbours; res: rounding error of phi (the f
 // populations sum to phi + res); qx, qy: phi_w u_w of this node at the previous step.
 // Writes the collided e_i into fo, the g deviations g*_i - g^eq_i(published moments) into
-// go and the published p_w, u_w into pw, or the moments into mom.
-template <int MODE>
+// go and the published p_w, u_w into pw, or the moments into mom.  FIRST: the state is the
+// initial one, f = f^eq(phi0, u0) and g = g^eq(p = 0, u0) at every node.
+template <int MODE, bool FIRST>
 __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&f)[9],
                                                 const float (&eg)[9], const float (&gs)[9],
                                                 float phi, float pE, float pN, float pW,
@@ -447,6 +478,35 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
 
     // d_t(phi u) as a backward difference over one step
     const C Dx = phi * cux - qx, Dy = phi * cuy - qy;
+
+    if (I.grad_scheme == GRAD_LOCAL_NEQ) {
+        // Eq. 29: n = -C/|C| with C = sum_i c_i (f_i - f_i^eq) + D/2.  On the rest
+        // deviations sum_i c_i (f_i - f_i^eq) = sum_i c_i e_i - phi u, so
+        // C = sum_i c_i e_i - (phi u + Q)/2 with Q = phi u of the previous step.
+        // On the initial state f = f^eq(phi0, u0), Q = phi0 u0 and sum_i c_i g_i = rho u0,
+        // so u - u0 = F/(2 rho) (Eq. 22a) and C = phi0 (u0 - u)/2 = -phi F/(4 rho) exactly.
+        // That C is of the order of the force, below the rounding of the stored first
+        // moment, so the first step takes the closed form.
+        C cx, cy;
+        if (FIRST) {
+            const C k = C(-0.25) * phi * C(irho);
+            cx = k * Fx;
+            cy = k * Fy;
+        } else {
+            const C ex = ((f[1] - f[3]) + (f[5] - f[7])) + (f[8] - f[6]);
+            const C ey = ((f[2] - f[4]) + (f[5] - f[7])) + (f[6] - f[8]);
+            cx = ex - C(0.5) * (phi * cux + qx);
+            cy = ey - C(0.5) * (phi * cuy + qy);
+        }
+        const C cm2 = cx * cx + cy * cy;
+        nx_ = C(0);
+        ny_ = C(0);
+        if (cm2 > C(1e-24)) {   // |C| > 1e-12
+            const C im = __builtin_amdgcn_rsqf(cm2);
+            nx_ = -cx * im;
+            ny_ = -cy * im;
+        }
+    }
 
     // f collision (Eqs. 8, 9, 11) on e_i = f_i - w_i phi.  The populations sum to phi + res
     // before and after the collision (sum f^eq = phi, sum F_i = 0); the rest population is
@@ -697,7 +757,7 @@ __device__ __forceinline__ void step_tile(
             }
             const int me = (yl + 2) * RW + lx + 2;
             const float qx = sw[me].x * sq[me].z, qy = sw[me].x * sq[me].w;
-            node_update_ref<MODE>(I, fd, eg, gs, phi, r1[2], r2[1], r1[0], r0[1], r2[2], r2[0],
+            node_update_ref<MODE, !PULL>(I, fd, eg, gs, phi, r1[2], r2[1], r1[0], r0[1], r2[2], r2[0],
                                   r0[0], r0[2], res[k], qx, qy, fo, go, pw, mom);
             if (MODE == MODE_STEP) {
 #pragma unroll

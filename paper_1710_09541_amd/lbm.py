@@ -30,7 +30,7 @@ EXPORTS = ("lbm_init", "lbm_step", "lbm_moments", "lbm_moments_device", "lbm_red
 class lbm_params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32),
                 ("bc_ylo", C.c_int32), ("bc_yhi", C.c_int32),
-                ("visc_law", C.c_int32), ("reserved0", C.c_int32),
+                ("visc_law", C.c_int32), ("grad_scheme", C.c_int32),
                 ("rho_l", C.c_double), ("rho_g", C.c_double),
                 ("nu_l", C.c_double), ("nu_g", C.c_double),
                 ("sigma", C.c_double), ("W", C.c_double), ("M", C.c_double),
@@ -109,6 +109,7 @@ def make_params(case, exp_f=LBM_EXP_AUTO, exp_g=LBM_EXP_AUTO) -> lbm_params:
     p.nx, p.ny = int(case["nx"]), int(case["ny"])
     p.bc_ylo, p.bc_yhi = int(case["bc_ylo"]), int(case["bc_yhi"])
     p.visc_law = int(case["visc_law"])
+    p.grad_scheme = int(case.get("grad_scheme", 0))
     for k in ("rho_l", "rho_g", "nu_l", "nu_g", "sigma", "W", "M", "Gx", "Gy"):
         setattr(p, k, float(case[k]))
     p.exp_f, p.exp_g = int(exp_f), int(exp_g)

@@ -61,7 +61,7 @@ def _init(case, **kw):
 
 
 @pytest.mark.parametrize("key,value", [("nx", 2), ("ny", 1), ("rho_g", 0.0), ("W", 0.0),
-                                       ("M", -1.0), ("nu_l", 0.0), ("visc_law", 9),
+                                       ("M", -1.0), ("nu_l", 0.0), ("visc_law", 9), ("grad_scheme", 2),
                                        ("sigma", -1.0), ("Gx", float("nan"))])
 def test_invalid_parameters_rejected_before_device(key, value):
     c = cases.static_drop(16, 16, R=4)

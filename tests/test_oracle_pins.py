@@ -527,3 +527,26 @@ def test_eq29_conserves_sum_phi():
     s.step(600)
     m1 = s.moments()["phi"].sum()
     assert abs(m1 - m0) / m0 < 20 * np.finfo(float).eps * 600
+
+
+@pytest.mark.parametrize("make", [lambda: cases.layered_poiseuille(),
+                                  lambda: cases.droplet_impact(128, 64, D=32, Re=20)])
+def test_eq29_first_collision_C_closed_form(make):
+    """On the initial state (f = f^eq(phi0, u0), g = g^eq(p = 0, u0), Q = phi0 u0) the
+    first moment C of Eq. 29 equals phi0 (u0 - u)/2 with u - u0 = F/(2 rho) from Eq. 22a,
+    i.e. C = -phi F/(4 rho): of the order of the force, far below the stored populations."""
+    c = make()
+    s = O.OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
+    f, g, q = s.get_state()
+    m = s.moments()
+    gx, gy, lap = O.stencil(c, m["phi"])
+    cx, cy, _, _ = _lat()
+    for y in range(0, c["ny"], 7):
+        for x in range(0, c["nx"], 5):
+            ph, ux, uy = m["phi"][y, x], m["ux"][y, x], m["uy"][y, x]
+            fe = O.feq(ph, ux, uy)
+            C = np.array([cx @ (f[:, y, x] - fe) + 0.5 * (ph * ux - q[0, y, x]),
+                          cy @ (f[:, y, x] - fe) + 0.5 * (ph * uy - q[1, y, x])])
+            cl = O.closure(c, ph, gx[y, x], gy[y, x], lap[y, x], g[:, y, x])
+            closed = -0.25 * ph * np.array([cl["F_x"], cl["F_y"]]) / cl["rho"]
+            assert np.all(np.abs(C - closed) < 1e-15)
