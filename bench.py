@@ -4,12 +4,21 @@ One step = one time step of both D2Q9 lattices (phase field f and flow g) over t
 workload.  The default workload is the spinodal-decomposition case: 1024 x 1024 periodic,
 phi0 = 0.5 + U[-0.01, 0.01] (seed 0), rho_l / rho_g = 3, sigma = 1e-3, W = 4, M = 0.1,
 nu_l = 0.1, nu_g = 1.0.  The headline value is MLUPS (million lattice-node updates of both
-lattices per second) with FP32 storage; FP64 and FP16-deviation storage are measured on
-the same device and reported next to it with their max-norm error against the FP64 CPU
-oracle over the same short horizon.
+lattices per second) with FP32 storage; FP64 and FP16-deviation storage are timed on the
+same device and reported next to it, each with its error against the FP64 CPU oracle:
+
+* on the benchmarked workload, over the oracle's timed sample: the coarsening length
+  L = 2 N / (phase-boundary crossings) and the drift of sum(phi) (the spinodal is chaotic,
+  so fields agree only statistically beyond a few steps; the FP64 format repeats the
+  oracle's arithmetic and its field error is reported as well);
+* field by field on the layered Poiseuille channel 16 x 512 after 1000 steps (walls,
+  step viscosity, density ratio 1000), where the stated tolerances apply.
+
+Also timed: the same spinodal at 4096 x 4096 (working set far above the 256 MB last-level
+cache, so the bandwidth is HBM's) and a batch of 256 independent instances of uneven size.
 
 Prints ONE JSON line.  Inputs are resident in device memory before the timed region;
-timing uses HIP events on the stream the library launches on.
+timing uses HIP events recorded on the stream the library launches on.
 """
 import argparse
 import hashlib
@@ -29,7 +38,12 @@ PEAK_HBM_GBS = 8000.0
 # written once, plus the per-node state beside them read and written once: FP64 phi u of
 # the previous step (2 doubles); reduced formats the FP32 planes phi_w, p_w, ux_w, uy_w
 ALG_BYTES = {"f64": 36 * 8 + 4 * 8, "f32": 36 * 4 + 8 * 4, "f16": 36 * 2 + 8 * 4}
+TOL = {"f64": 1e-12, "f32": 1e-5, "f16": 1e-3}
 KERNEL_SRC = os.path.join(ROOT, "paper_1710_09541_amd", "csrc", "lbm_kernels.hip")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():
@@ -46,17 +60,18 @@ def workload(name):
         return [c], desc
     if name == "spinodal4096":
         c = cases.spinodal(4096, seed=0)
-        return [c], "spinodal decomposition 4096x4096 periodic (HBM-resident working set)"
+        return [c], "spinodal decomposition 4096x4096 periodic, as spinodal1024 otherwise"
     if name == "impact2048":
         c = cases.droplet_impact(2048, 512, D=256, Re=100)
         return [c], "droplet impact on a film 2048x512, D=256, Re=100, We=8000, ratio 1000"
     if name == "batch256":
         cs = cases.batch_ensemble(256, seed=1)
-        return cs, "256 static-drop / layered-Poiseuille instances, grids 32..512 (seed 1)"
+        return cs, ("256 static-drop / layered-Poiseuille instances, grids uniform in 32..512 "
+                    "per axis, density ratio 10/100/1000 (seed 1)")
     raise SystemExit("unknown workload " + name)
 
 
-def traffic_from_profile(wl, storage, nodes):
+def traffic_from_profile(wl, storage):
     """HBM bytes per launch from the committed rocprofv3 counter summary, scaled by the
     copy-kernel calibration; None if absent or taken on another version of the kernels."""
     path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (wl, storage))
@@ -89,22 +104,63 @@ def time_gpu(cs, storage, steps, warmup, kernel, tile_rows):
     return ms, info
 
 
-def gpu_error(cs, storage, nsteps, ref):
+def measure(cs, storage, steps, warmup, kernel="auto", tile_rows=0):
+    nodes = sum(c["nx"] * c["ny"] for c in cs)
+    ms, info = time_gpu(cs, storage, steps, warmup, kernel, tile_rows)
+    per_launch_s = ms / 1e3 / steps
+    ach = ALG_BYTES[storage] * nodes / per_launch_s / 1e9
+    return {"mlups": nodes * steps / (ms / 1e3) / 1e6, "ms_per_step": ms / steps,
+            "kernel": info["kernel"], "tile_rows": info["tile_rows"],
+            "alg_bytes_per_lu": ALG_BYTES[storage], "achieved_gbs": ach,
+            "frac_hbm_peak": ach / PEAK_HBM_GBS, "nodes": nodes, "steps": steps}
+
+
+def crossings_length(phi):
+    n = phi.size
+    s = phi >= 0.5
+    cr = np.count_nonzero(s != np.roll(s, 1, axis=1)) + np.count_nonzero(s != np.roll(s, 1, axis=0))
+    return 2.0 * n / max(cr, 1)
+
+
+def spinodal_accuracy(c, storage, nsteps, ref):
+    """L and sum(phi) drift of the GPU run against the oracle's, plus the field error."""
     from paper_1710_09541_amd import lbm
     from tests.parity import errors
-    with lbm.Simulation(cs, storage=storage) as sim:
+    with lbm.Simulation([c], storage=storage) as sim:
+        s0 = float(sim.moments(0)["phi"].sum())
         sim.step(nsteps)
         got = sim.moments(0)
-    return errors(cs[0], got, ref)
+    L_gpu, L_ref = crossings_length(got["phi"]), crossings_length(ref["phi"])
+    e = errors(c, got, ref)
+    return {"steps": nsteps, "L": L_gpu, "L_oracle": L_ref, "L_rel_err": abs(L_gpu / L_ref - 1),
+            "sum_phi_drift": abs(float(got["phi"].sum()) - s0) / s0,
+            "field_max_err": {k: e[k] for k in ("phi", "u", "p")}}
 
 
-def cpu_baseline(cs, steps):
+def poiseuille_parity(storage, ref_cache):
+    from paper_1710_09541_amd import cases, lbm
+    from tests.parity import errors, run_oracle
+    c = cases.layered_poiseuille()
+    if "pois" not in ref_cache:
+        ref_cache["pois"] = run_oracle(c, 1000)
+    with lbm.Simulation([c], storage=storage) as sim:
+        sim.step(1000)
+        got = sim.moments(0)
+    e = errors(c, got, ref_cache["pois"])
+    return {"case": "layered Poiseuille 16x512, ratio 1000, step mu, 1000 steps",
+            "phi": e["phi"], "u": e["u"], "p": e["p"], "tol": TOL[storage],
+            "within_tol": bool(e["u"] <= TOL[storage] and
+                               (storage == "f16" or e["phi"] <= TOL[storage]))}
+
+
+def cpu_baseline(c, steps):
+    """The FP64 oracle timed on this host's cores over a bounded sample of the workload."""
     from oracle.oracle import OracleSim
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count()
-    c = cs[0]
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
     s = OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
     s.step(1)
     t0 = time.perf_counter()
@@ -112,9 +168,11 @@ def cpu_baseline(cs, steps):
     dt = time.perf_counter() - t0
     nodes = c["nx"] * c["ny"]
     ref = s.moments()
-    return {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": "%dx%d, %d steps after 1 warm-up step, FP64, OpenMP over rows, %.1f s"
-                      % (c["nx"], c["ny"], steps, dt)}, ref
+    return {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": min(cores, threads),
+            "kind": "oracle",
+            "sample": "%dx%d spinodal, %d steps after 1 untimed step, FP64, OpenMP over rows "
+                      "(%d threads), %.1f s" % (c["nx"], c["ny"], steps, min(cores, threads), dt)
+            }, ref
 
 
 def main():
@@ -126,15 +184,18 @@ def main():
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--kernel", default="auto")
     ap.add_argument("--tile-rows", type=int, default=0)
-    ap.add_argument("--variants", default="f64,f16", help="other storages to time ('' for none)")
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--variants", default="f64,f16", help="other storages to time ('none' for none)")
+    ap.add_argument("--cpu-steps", type=int, default=1500,
+                    help="oracle steps of the CPU baseline (also the accuracy horizon)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 4096^2 and 256-instance batch measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: this implementation has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
@@ -157,35 +218,49 @@ def main():
 
     cs, desc = workload(args.workload)
     nodes = sum(c["nx"] * c["ny"] for c in cs)
-    print("[bench] workload %s, %d nodes, storage %s" % (args.workload, nodes, args.storage),
-          file=sys.stderr, flush=True)
+    log("workload %s, %d nodes, storage %s" % (args.workload, nodes, args.storage))
 
     base = None
     ref = None
-    if not args.no_cpu_baseline and len(cs) == 1:
-        base, ref = cpu_baseline(cs, args.cpu_steps)
-        print("[bench] cpu baseline %.2f MLUPS (%s)" % (base["value"], base["sample"]),
-              file=sys.stderr, flush=True)
+    single = len(cs) == 1 and cs[0].get("name") == "spinodal"
+    if not args.no_cpu_baseline and single:
+        base, ref = cpu_baseline(cs[0], args.cpu_steps)
+        log("cpu baseline %.2f MLUPS (%s)" % (base["value"], base["sample"]))
 
     results = {}
-    for st in [args.storage] + [v for v in args.variants.split(",") if v and v != args.storage]:
-        ms, info = time_gpu(cs, st, args.steps, args.warmup, args.kernel, args.tile_rows)
-        mlups = nodes * args.steps / (ms / 1e3) / 1e6
-        per_launch_s = ms / 1e3 / args.steps
-        ach = ALG_BYTES[st] * nodes / per_launch_s / 1e9
-        r = {"mlups": mlups, "ms_per_step": ms / args.steps, "kernel": info["kernel"],
-             "tile_rows": info["tile_rows"], "alg_bytes_per_lu": ALG_BYTES[st],
-             "achieved_gbs": ach, "frac_hbm_peak": ach / PEAK_HBM_GBS}
+    pois_ref = {}
+    others = [] if args.variants in ("", "none") else args.variants.split(",")
+    for st in [args.storage] + [v for v in others if v and v != args.storage]:
+        r = measure(cs, st, args.steps, args.warmup, args.kernel, args.tile_rows)
+        log("%s: %.1f MLUPS, %.4f ms/step, %.0f GB/s algorithmic" % (st, r["mlups"],
+                                                                      r["ms_per_step"],
+                                                                      r["achieved_gbs"]))
         if ref is not None:
-            e = gpu_error(cs, st, args.cpu_steps + 1, ref)
-            r["max_norm_error_vs_oracle"] = {"steps": args.cpu_steps + 1, **e}
+            r["accuracy_vs_oracle"] = spinodal_accuracy(cs[0], st, args.cpu_steps + 1, ref)
+            log("%s: accuracy %s" % (st, json.dumps(r["accuracy_vs_oracle"])))
+        if not args.no_cpu_baseline:
+            r["parity_vs_oracle"] = poiseuille_parity(st, pois_ref)
+            log("%s: parity %s" % (st, json.dumps(r["parity_vs_oracle"])))
         results[st] = r
-        print("[bench] %s: %.1f MLUPS, %.4f ms/step, %.0f GB/s algorithmic (%s)"
-              % (st, mlups, ms / args.steps, ach, info), file=sys.stderr, flush=True)
+
+    extra = {}
+    if not args.no_extra and args.workload == "spinodal1024":
+        big, bdesc = workload("spinodal4096")
+        for st in ("f32", "f64", "f16"):
+            r = measure(big, st, 1000, 20)
+            extra["spinodal4096_" + st] = r
+            log("4096^2 %s: %.1f MLUPS, %.0f GB/s algorithmic" % (st, r["mlups"], r["achieved_gbs"]))
+        del big
+        bcs, bdesc = workload("batch256")
+        for st in ("f32", "f64"):
+            r = measure(bcs, st, 200, 10)
+            r["workload"] = bdesc
+            extra["batch256_" + st] = r
+            log("batch256 %s: %.1f MLUPS over %d nodes, %.0f GB/s algorithmic"
+                % (st, r["mlups"], r["nodes"], r["achieved_gbs"]))
 
     main_r = results[args.storage]
     kname = {1: "k_step (fused)", 2: "k_phi_plane + k_step (split)"}[main_r["kernel"]]
-    traffic = traffic_from_profile(args.workload, args.storage, nodes)
     out = {
         "metric": METRIC,
         "value": round(main_r["mlups"], 2),
@@ -203,11 +278,13 @@ def main():
                    "kernel": kname, "tile_rows": main_r["tile_rows"]},
         "roofline": {"bound": "hbm", "achieved": round(main_r["achieved_gbs"], 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(main_r["frac_hbm_peak"], 4), "traffic": traffic,
+                     "frac": round(main_r["frac_hbm_peak"], 4),
+                     "traffic": traffic_from_profile(args.workload, args.storage),
                      "kernel": kname,
                      "alg_bytes_per_launch": ALG_BYTES[args.storage] * nodes},
         "cpu_baseline": base,
-        "variants": {k: v for k, v in results.items()},
+        "variants": results,
+        "extra": extra,
         "kernel_source_sha256": kernel_source_hash(),
     }
     print(json.dumps(out), flush=True)
