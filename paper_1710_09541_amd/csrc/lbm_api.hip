@@ -105,6 +105,18 @@ int hip_fail(lbm_ctx* c, hipError_t e, const char* what) {
 
 int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
+// copies and fills that accept empty buffers (a format does not allocate the other
+// format's state planes)
+hipError_t copy_n(void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+    return bytes ? hipMemcpy(dst, src, bytes, kind) : hipSuccess;
+}
+hipError_t copy_n_async(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st) : hipSuccess;
+}
+hipError_t zero_n_async(void* dst, size_t bytes, hipStream_t st) {
+    return bytes ? hipMemsetAsync(dst, 0, bytes, st) : hipSuccess;
+}
+
 int list_index(int rows) { return rows == 4 ? 0 : (rows == 8 ? 1 : (rows == 16 ? 2 : -1)); }
 
 std::string check_params(const lbm_params& p, int k) {
@@ -353,8 +365,7 @@ int autotune(lbm_ctx* c) {
         c->tile_rows = cands[0].rows;
         return LBM_OK;
     }
-    HIPCHK(c, hipMemcpyAsync(c->q_tune, c->q, c->q_elems * sizeof(double),
-                             hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, copy_n_async(c->q_tune, c->q, c->q_elems * sizeof(double), c->stream));
     // temporary copy of the current buffers
     void *tf = nullptr, *tg = nullptr, *tr = nullptr;
     const size_t dbytes = (size_t)c->dist_elems * c->esize;
@@ -365,9 +376,7 @@ int autotune(lbm_ctx* c) {
     if (alt) {
         HIPCHK(c, hipMemcpyAsync(tf, c->f[c->cur], dbytes, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(tg, c->g[c->cur], dbytes, hipMemcpyDeviceToDevice, c->stream));
-        if (rbytes)
-            HIPCHK(c, hipMemcpyAsync(tr, c->rplane[c->cur], rbytes, hipMemcpyDeviceToDevice,
-                                     c->stream));
+        HIPCHK(c, copy_n_async(tr, c->rplane[c->cur], rbytes, c->stream));
     }
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
@@ -478,9 +487,13 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
         I.d.off_phi = off_phi;
         I.d.off_mp = off_mp;
         off_dist += round_up(9 * I.d.plane, 64);
-        off_q += round_up(2 * I.d.plane, 64);
+        // phi u of the previous step: two double planes (FP64 format) or, in the reduced
+        // formats, the four FP32 planes phi_w, p_w, u_w that also carry it
+        if (c->storage == STORE_F64)
+            off_q += round_up(2 * I.d.plane, 64);
+        else
+            off_mp += round_up(4 * I.d.plane, 64);
         off_phi += round_up(I.d.plane, 64);
-        off_mp += round_up(4 * I.d.plane, 64);
         c->max_nodes = std::max(c->max_nodes, I.n_nodes);
     }
     c->dist_elems = off_dist;
@@ -526,6 +539,8 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
         {(void**)&c->red_out, 16 * sizeof(double)},
     };
     for (auto& a : allocs) {
+        *a.ptr = nullptr;
+        if (a.bytes == 0) continue;   // a buffer this format does not use
         e = hipMalloc(a.ptr, a.bytes);
         if (e != hipSuccess) {
             fail(c, LBM_ERR_ALLOC, std::string("device allocation failed: ") + hipGetErrorString(e));
@@ -539,10 +554,9 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
         hipMemsetAsync(c->f[i], 0, dist_bytes, c->stream);
         hipMemsetAsync(c->g[i], 0, dist_bytes, c->stream);
     }
-    hipMemsetAsync(c->phiplane, 0, c->phi_elems * c->qsize, c->stream);
-    hipMemsetAsync(c->q, 0, c->q_elems * sizeof(double), c->stream);
-    for (int i = 0; i < 2; ++i)
-        hipMemsetAsync(c->rplane[i], 0, c->mp_elems * sizeof(float), c->stream);
+    zero_n_async(c->phiplane, c->phi_elems * c->qsize, c->stream);
+    zero_n_async(c->q, c->q_elems * sizeof(double), c->stream);
+    for (int i = 0; i < 2; ++i) zero_n_async(c->rplane[i], c->mp_elems * sizeof(float), c->stream);
 
     std::vector<InstDev> hd(n_inst);
     for (int k = 0; k < n_inst; ++k) hd[k] = c->inst[k].d;
@@ -715,8 +729,8 @@ int lbm_get_state(lbm_ctx* c, void* buf, size_t* bytes) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(b + sizeof h, c->f[c->cur], bd, hipMemcpyDeviceToHost));
     HIPCHK(c, hipMemcpy(b + sizeof h + bd, c->g[c->cur], bd, hipMemcpyDeviceToHost));
-    HIPCHK(c, hipMemcpy(b + sizeof h + 2 * bd, c->q, bq, hipMemcpyDeviceToHost));
-    HIPCHK(c, hipMemcpy(b + sizeof h + 2 * bd + bq, c->rplane[c->cur], bp, hipMemcpyDeviceToHost));
+    HIPCHK(c, copy_n(b + sizeof h + 2 * bd, c->q, bq, hipMemcpyDeviceToHost));
+    HIPCHK(c, copy_n(b + sizeof h + 2 * bd + bq, c->rplane[c->cur], bp, hipMemcpyDeviceToHost));
     *bytes = total;
     return LBM_OK;
 }
@@ -737,8 +751,8 @@ int lbm_set_state(lbm_ctx* c, const void* buf, size_t bytes) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(c->f[0], b + sizeof h, bd, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->g[0], b + sizeof h + bd, bd, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->q, b + sizeof h + 2 * bd, bq, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->rplane[0], b + sizeof h + 2 * bd + bq, bp, hipMemcpyHostToDevice));
+    HIPCHK(c, copy_n(c->q, b + sizeof h + 2 * bd, bq, hipMemcpyHostToDevice));
+    HIPCHK(c, copy_n(c->rplane[0], b + sizeof h + 2 * bd + bq, bp, hipMemcpyHostToDevice));
     c->cur = 0;
     c->streamed = h.streamed != 0;
     c->step = h.step;
