@@ -550,3 +550,21 @@ def test_eq29_first_collision_C_closed_form(make):
             cl = O.closure(c, ph, gx[y, x], gy[y, x], lap[y, x], g[:, y, x])
             closed = -0.25 * ph * np.array([cl["F_x"], cl["F_y"]]) / cl["rho"]
             assert np.all(np.abs(C - closed) < 1e-15)
+
+
+def test_impact_spreading_power_law():
+    """Sec. 3.4: after impact the spreading radius grows as r/D = C sqrt(tU/D) with
+    C about 1.35 (the paper's fit).  At the oracle's size (512 x 128, D = 64, Re = 100,
+    We = 8000, ratio 1000) the fitted C over t* = 0.5..2 lies within 20 % of it.  (The
+    spreading radius is read on the row y = H_w + W, as the paper does not define it.)"""
+    c = cases.droplet_impact(512, 128, D=64, Re=100)
+    s = O.OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
+    T = c["D"] / c["U"]
+    ratios = []
+    for t in (0.5, 1.0, 1.5, 2.0):
+        s.step(int(round(t * T)) - s.steps)
+        d = diag.diagnostics(s.moments(), c["rho_l"], c["rho_g"], c["mask"], periodic_y=False)
+        assert d["nonfinite"] == 0
+        ratios.append(d["spread_radius"] / c["D"] / np.sqrt(t))
+    C = float(np.mean(ratios))
+    assert abs(C / 1.35 - 1) < 0.2
