@@ -661,6 +661,37 @@ __device__ __forceinline__ void step_tile(
             for (int i = 0; i < 9; ++i) g[k][i] = Store<S>::get(gb, o[i]);
         }
     }
+    // halo ring: top row, bottom row (w + 2 each), left and right columns (h each); the
+    // ring's populations are requested together with the node's own
+    const int ring = 2 * (w + 2) + 2 * h;
+    const bool on_ring = tid < ring;
+    int rx = 0, ry = 0, rgx = 0, rgy = 0, ryraw = 0;
+    C rfv[9];
+    if (on_ring) {
+        if (tid < w + 2) {
+            rx = tid - 1;
+            ry = -1;
+        } else if (tid < 2 * (w + 2)) {
+            rx = tid - (w + 2) - 1;
+            ry = h;
+        } else if (tid < 2 * (w + 2) + h) {
+            rx = -1;
+            ry = tid - 2 * (w + 2);
+        } else {
+            rx = w;
+            ry = tid - 2 * (w + 2) - h;
+        }
+        rgx = T.x0 + rx;
+        if (!INTERIOR) rgx = rgx < 0 ? rgx + nx : (rgx >= nx ? rgx - nx : rgx);
+        ryraw = T.y0 + ry;
+        rgy = INTERIOR ? ryraw : ghost_row(I, ryraw);
+        if (!RING_FROM_PLANE) {
+            int o[9], src[9];
+            pull_offsets<PULL, INTERIOR>(I, rgx, rgy, o, src);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) rfv[i] = Store<S>::get(fb, o[i]);
+        }
+    }
     if (REF) __syncthreads();
 
     // phi of the tile's own nodes (and, reduced formats, its rounding residual)
@@ -681,39 +712,14 @@ __device__ __forceinline__ void step_tile(
             sphi[(yl + 1) * LW + lx + 1] = phi_of<C, REF>(f[k], ref, base, isf, &res[k]);
         }
     }
-    // halo ring: top row, bottom row (w + 2 each), left and right columns (h each)
-    const int ring = 2 * (w + 2) + 2 * h;
-    if (tid < ring) {
-        int rx, ry;
-        if (tid < w + 2) {
-            rx = tid - 1;
-            ry = -1;
-        } else if (tid < 2 * (w + 2)) {
-            rx = tid - (w + 2) - 1;
-            ry = h;
-        } else if (tid < 2 * (w + 2) + h) {
-            rx = -1;
-            ry = tid - 2 * (w + 2);
-        } else {
-            rx = w;
-            ry = tid - 2 * (w + 2) - h;
-        }
-        int gx = T.x0 + rx;
-        if (!INTERIOR) gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
-        const int yraw = T.y0 + ry;
-        const int gy = INTERIOR ? yraw : ghost_row(I, yraw);
+    if (on_ring) {
+        const int gx = rgx, gy = rgy, yraw = ryraw;
         C v;
         if (RING_FROM_PLANE) {
             v = phiplane[I.off_phi + gy * pitch + gx];
         } else {
-            int o[9], src[9];
-            pull_offsets<PULL, INTERIOR>(I, gx, gy, o, src);
-            C fv[9], ref[9], base = C(0);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) fv[i] = Store<S>::get(fb, o[i]);
+            C ref[9], base = C(0);
             if (REF) {
-                // a mirrored ghost row is the edge row itself; a wrapped one keeps its
-                // unwrapped position (the staged halo holds the wrapped values)
                 const bool mirrored = (yraw < 0 && I.bc_lo != BC_PERIODIC) ||
                                       (yraw >= ny && I.bc_hi != BC_PERIODIC);
                 const int lyl = mirrored ? gy - T.y0 : ry;
@@ -723,7 +729,7 @@ __device__ __forceinline__ void step_tile(
                 for (int i = 0; i < 9; ++i) ref[i] = sw[r[i]].x;
                 base = sw[(lyl + 2) * RW + rx + 2].x;
             }
-            v = phi_of<C, REF>(fv, ref, base, isf);
+            v = phi_of<C, REF>(rfv, ref, base, isf);
         }
         sphi[(ry + 1) * LW + rx + 1] = v;
     }
