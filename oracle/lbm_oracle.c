@@ -15,6 +15,8 @@
  * Notation follows the paper: f_i is the phase-field (conservative Allen-Cahn)
  * distribution with relaxation time tau_f (called tau_phi here), g_i is the flow
  * distribution with relaxation time tau_g.  Lattice units: dx = dt = 1, c_s^2 = 1/3.
+ * The phase field runs on D2Q9 (the paper's choice) or on D2Q5 (which Sec. 2.2 also
+ * admits); the flow lattice and the stencils of Eqs. 27-28 are always D2Q9.
  *
  * One step n -> n+1 (state = post-streaming f, g and Q = (phi u) of the previous step):
  *   S1  phi = sum_i f_i                                    (Sec. 2.2, Eq. 12)
@@ -44,6 +46,12 @@ static const double WGT[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0
                               1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 /* opposite direction: c_opp(i) = -c_i */
 static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+/* D2Q5 for the phase field (Sec. 2.2 allows it): the rest and the four axis velocities,
+ * i = 0..4 as above, weights 1/3 and 1/6, the same c_s^2 = 1/3 (sum w_i c_i c_i = I/3). */
+static const double WGT5[5] = {1.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0};
+
+/* weights of the phase-field lattice with qf velocities (9 or 5) */
+static const double* fweights(int qf) { return qf == 5 ? WGT5 : WGT; }
 /* c_s^2 = 1/3 (c = 1); its reciprocal 3 and the derived factors 1/(2 c_s^4) = 9/2,
  * 1/(2 c_s^2) = 3/2 and c_s^2/(1 - w_0) = 3/5 are written as exact constants, so no rounded
  * 1/3 enters the arithmetic. */
@@ -64,6 +72,8 @@ typedef struct {
     double nu_l, nu_g;       /* phase kinematic viscosities */
     double sigma, W, M;      /* surface tension, interface width, mobility */
     double Gx, Gy;           /* body-force density G (Eq. 4b) */
+    int32_t f_lattice;       /* velocities of the phase-field lattice: 9 (D2Q9) or 5 (D2Q5) */
+    int32_t reserved;
 } orc_params;
 
 typedef struct {
@@ -82,11 +92,12 @@ typedef struct {
 
 /* --------------------------------------------------------------- local formulas */
 
-/* f_i^eq = w_i phi (1 + c_i.u / c_s^2)  (Eq. 9) */
-static void feq_node(double phi, double ux, double uy, double out[9]) {
-    for (int i = 0; i < 9; ++i) {
+/* f_i^eq = w_i phi (1 + c_i.u / c_s^2)  (Eq. 9), i < qf */
+static void feq_node(int qf, double phi, double ux, double uy, double out[9]) {
+    const double* w = fweights(qf);
+    for (int i = 0; i < qf; ++i) {
         double cu = CX[i] * ux + CY[i] * uy;
-        out[i] = WGT[i] * phi * (1.0 + cu * INV_CS2);
+        out[i] = w[i] * phi * (1.0 + cu * INV_CS2);
     }
 }
 
@@ -105,12 +116,13 @@ static void geq_node(double p, double rho, double ux, double uy, double out[9]) 
 
 /* F_i = (1 - 1/(2 tau_f)) w_i c_i.[d_t(phi u) + c_s^2 lambda n] / c_s^2  (Eq. 11),
  * i.e. (1 - 1/(2 tau_f)) w_i c_i.[d_t(phi u) / c_s^2 + lambda n] */
-static void fsource_node(double tau_f, double dtx, double dty, double lambda, double nx_,
-                         double ny_, double out[9]) {
+static void fsource_node(int qf, double tau_f, double dtx, double dty, double lambda,
+                         double nx_, double ny_, double out[9]) {
+    const double* w = fweights(qf);
     double vx = dtx * INV_CS2 + lambda * nx_;
     double vy = dty * INV_CS2 + lambda * ny_;
-    for (int i = 0; i < 9; ++i)
-        out[i] = (1.0 - 1.0 / (2.0 * tau_f)) * WGT[i] * (CX[i] * vx + CY[i] * vy);
+    for (int i = 0; i < qf; ++i)
+        out[i] = (1.0 - 1.0 / (2.0 * tau_f)) * w[i] * (CX[i] * vx + CY[i] * vy);
 }
 
 /* G_i = (1 - 1/(2 tau_g)) w_i [c_i.F / c_s^2 + (rho_l - rho_g) u grad(phi) : c_i c_i / c_s^2]
@@ -187,10 +199,10 @@ static void stencil_node(const orc_params* p, const double* phi, int x, int y, d
  * C = 0 (every node of an equilibrium state) and cancels badly where |C| << B.  Where
  * |C| does not exceed 1e-12 the direction is undefined and n is taken as zero, as for the
  * isotropic scheme. */
-static void normal_local_neq(const double f[9], const double fe[9], double dtx, double dty,
-                             double* nx_, double* ny_) {
+static void normal_local_neq(int qf, const double f[9], const double fe[9], double dtx,
+                             double dty, double* nx_, double* ny_) {
     double cx = 0.0, cy = 0.0;
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 0; i < qf; ++i) {
         cx += CX[i] * (f[i] - fe[i]);
         cy += CY[i] * (f[i] - fe[i]);
     }
@@ -255,10 +267,11 @@ static void closure_node(const orc_sim* s, double phi, double dpx, double dpy, d
 
 static void compute_phi(orc_sim* s) {
     const int64_t n = s->n;
+    const int qf = s->p.f_lattice;
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < n; ++k) {
         double acc = 0.0;
-        for (int i = 0; i < 9; ++i) acc += s->f[(int64_t)i * n + k];
+        for (int i = 0; i < qf; ++i) acc += s->f[(int64_t)i * n + k];
         s->phi[k] = acc;                                                      /* Eq. 12 */
     }
 }
@@ -273,6 +286,7 @@ static void gather(const double* a, int64_t n, int64_t k, double out[9]) {
 static void step_once(orc_sim* s) {
     const orc_params* p = &s->p;
     const int nx = p->nx, ny = p->ny;
+    const int qf = p->f_lattice;
     const int64_t n = s->n;
     compute_phi(s);                                                           /* S1 */
 
@@ -296,11 +310,11 @@ static void step_once(orc_sim* s) {
 
             /* S7: f_i* = f_i - (f_i - f_i^eq)/tau_f + F_i  (Eq. 8) */
             double fe[9], fs[9], fpost[9];
-            feq_node(o.phi, o.ux, o.uy, fe);
+            feq_node(qf, o.phi, o.ux, o.uy, fe);
             if (p->grad_scheme == ORC_GRAD_LOCAL_NEQ)                        /* Eq. 29 */
-                normal_local_neq(f, fe, dtx, dty, &o.nx, &o.ny);
-            fsource_node(s->tau_f, dtx, dty, o.lambda, o.nx, o.ny, fs);
-            for (int i = 0; i < 9; ++i) fpost[i] = f[i] - (f[i] - fe[i]) / s->tau_f + fs[i];
+                normal_local_neq(qf, f, fe, dtx, dty, &o.nx, &o.ny);
+            fsource_node(qf, s->tau_f, dtx, dty, o.lambda, o.nx, o.ny, fs);
+            for (int i = 0; i < qf; ++i) fpost[i] = f[i] - (f[i] - fe[i]) / s->tau_f + fs[i];
 
             /* S8: g_i* = g_i - (g_i - g_i^eq)/tau_g + G_i  (Eq. 15) */
             double ge[9], gf[9], gpost[9];
@@ -317,10 +331,10 @@ static void step_once(orc_sim* s) {
                 int side = yd < 0 ? p->bc_ylo : (yd >= ny ? p->bc_yhi : -1);
                 if (side == -1 || side == ORC_PERIODIC) {
                     yd = wrap(yd, ny);
-                    s->fn[AT(i, yd, xd, nx, ny)] = fpost[i];
+                    if (i < qf) s->fn[AT(i, yd, xd, nx, ny)] = fpost[i];
                     s->gn[AT(i, yd, xd, nx, ny)] = gpost[i];
                 } else if (side == ORC_WALL) {
-                    s->fn[AT(OPP[i], y, x, nx, ny)] = fpost[i];
+                    if (i < qf) s->fn[AT(OPP[i], y, x, nx, ny)] = fpost[i];
                     s->gn[AT(OPP[i], y, x, nx, ny)] = gpost[i];
                 } /* ORC_OPEN: the population leaves the domain */
             }
@@ -333,7 +347,7 @@ static void step_once(orc_sim* s) {
         for (int i = 0; i < 9; ++i) {
             if (CY[i] >= 0) continue;
             for (int x = 0; x < nx; ++x) {
-                s->fn[AT(i, ny - 1, x, nx, ny)] = s->fn[AT(i, ny - 2, x, nx, ny)];
+                if (i < qf) s->fn[AT(i, ny - 1, x, nx, ny)] = s->fn[AT(i, ny - 2, x, nx, ny)];
                 s->gn[AT(i, ny - 1, x, nx, ny)] = s->gn[AT(i, ny - 2, x, nx, ny)];
             }
         }
@@ -342,7 +356,7 @@ static void step_once(orc_sim* s) {
         for (int i = 0; i < 9; ++i) {
             if (CY[i] <= 0) continue;
             for (int x = 0; x < nx; ++x) {
-                s->fn[AT(i, 0, x, nx, ny)] = s->fn[AT(i, 1, x, nx, ny)];
+                if (i < qf) s->fn[AT(i, 0, x, nx, ny)] = s->fn[AT(i, 1, x, nx, ny)];
                 s->gn[AT(i, 0, x, nx, ny)] = s->gn[AT(i, 1, x, nx, ny)];
             }
         }
@@ -366,6 +380,7 @@ int orc_check(const orc_params* p) {
     if (p->bc_ylo < 0 || p->bc_ylo > 2 || p->bc_yhi < 0 || p->bc_yhi > 2) return -3;
     if (p->visc_law < 0 || p->visc_law > 2) return -4;
     if (p->grad_scheme < 0 || p->grad_scheme > 1) return -7;
+    if (p->f_lattice != 9 && p->f_lattice != 5) return -8;
     if (!(p->rho_l > 0) || !(p->rho_g > 0) || !(p->nu_l > 0) || !(p->nu_g > 0)) return -5;
     if (!(p->W > 0) || !(p->M > 0) || !(p->sigma >= 0)) return -6;
     return 0;
@@ -399,11 +414,11 @@ orc_sim* orc_create(const orc_params* p, const double* phi0, const double* ux0,
     for (int64_t k = 0; k < s->n; ++k) {
         double ph = phi0[k], ux = ux0[k], uy = uy0[k];
         double rho = ph * (p->rho_l - p->rho_g) + p->rho_g;
-        double fe[9], ge[9];
-        feq_node(ph, ux, uy, fe);
+        double fe[9] = {0.0}, ge[9];
+        feq_node(p->f_lattice, ph, ux, uy, fe);
         geq_node(0.0, rho, ux, uy, ge);
         for (int i = 0; i < 9; ++i) {
-            s->f[(int64_t)i * s->n + k] = fe[i];
+            s->f[(int64_t)i * s->n + k] = fe[i];   /* planes qf..8 unused (zero) for D2Q5 */
             s->g[(int64_t)i * s->n + k] = ge[i];
         }
         s->q[k] = ph * ux;
@@ -471,15 +486,23 @@ void orc_lattice(int32_t* cx, int32_t* cy, double* w, int32_t* opp) {
     }
 }
 
-void orc_feq(double phi, double ux, double uy, double* out) { feq_node(phi, ux, uy, out); }
+void orc_feq(int32_t qf, double phi, double ux, double uy, double* out) {
+    feq_node(qf, phi, ux, uy, out);
+}
 
 void orc_geq(double p, double rho, double ux, double uy, double* out) {
     geq_node(p, rho, ux, uy, out);
 }
 
-void orc_fsource(double tau_f, double dtx, double dty, double lambda, double nx_, double ny_,
-                 double* out) {
-    fsource_node(tau_f, dtx, dty, lambda, nx_, ny_, out);
+void orc_fsource(int32_t qf, double tau_f, double dtx, double dty, double lambda, double nx_,
+                 double ny_, double* out) {
+    fsource_node(qf, tau_f, dtx, dty, lambda, nx_, ny_, out);
+}
+
+/* weights of the phase-field lattice with qf velocities (its velocities are c_0..c_{qf-1}) */
+void orc_fweights(int32_t qf, double* w) {
+    const double* src = fweights(qf);
+    for (int i = 0; i < qf; ++i) w[i] = src[i];
 }
 
 void orc_gforce(double tau_g, double Fx, double Fy, double drho, double ux, double uy,
@@ -516,9 +539,9 @@ void orc_closure(const orc_params* p, double phi, double dpx, double dpy, double
 }
 
 /* Eq. 29 normal at one node from its f_i, phi, u and d_t(phi u); out = {n_x, n_y}. */
-void orc_normal_local_neq(const double* f, double phi, double ux, double uy, double dtx,
-                          double dty, double* out) {
+void orc_normal_local_neq(int32_t qf, const double* f, double phi, double ux, double uy,
+                          double dtx, double dty, double* out) {
     double fe[9];
-    feq_node(phi, ux, uy, fe);
-    normal_local_neq(f, fe, dtx, dty, &out[0], &out[1]);
+    feq_node(qf, phi, ux, uy, fe);
+    normal_local_neq(qf, f, fe, dtx, dty, &out[0], &out[1]);
 }

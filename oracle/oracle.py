@@ -22,7 +22,8 @@ class OrcParams(C.Structure):
                 ("rho_l", C.c_double), ("rho_g", C.c_double),
                 ("nu_l", C.c_double), ("nu_g", C.c_double),
                 ("sigma", C.c_double), ("W", C.c_double), ("M", C.c_double),
-                ("Gx", C.c_double), ("Gy", C.c_double)]
+                ("Gx", C.c_double), ("Gy", C.c_double),
+                ("f_lattice", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -48,13 +49,14 @@ def lib():
         L.orc_set_state.argtypes = [C.c_void_p, _D, _D, _D]
         L.orc_lattice.argtypes = [C.POINTER(C.c_int32), C.POINTER(C.c_int32), _D,
                                   C.POINTER(C.c_int32)]
-        L.orc_feq.argtypes = [C.c_double] * 3 + [_D]
+        L.orc_feq.argtypes = [C.c_int32] + [C.c_double] * 3 + [_D]
         L.orc_geq.argtypes = [C.c_double] * 4 + [_D]
-        L.orc_fsource.argtypes = [C.c_double] * 6 + [_D]
+        L.orc_fsource.argtypes = [C.c_int32] + [C.c_double] * 6 + [_D]
+        L.orc_fweights.argtypes = [C.c_int32, _D]
         L.orc_gforce.argtypes = [C.c_double] * 8 + [_D]
         L.orc_stencil.argtypes = [P, _D, _D, _D, _D]
         L.orc_closure.argtypes = [P] + [C.c_double] * 4 + [_D, _D]
-        L.orc_normal_local_neq.argtypes = [_D] + [C.c_double] * 5 + [_D]
+        L.orc_normal_local_neq.argtypes = [C.c_int32, _D] + [C.c_double] * 5 + [_D]
         _lib = L
     return _lib
 
@@ -66,6 +68,7 @@ def make_params(case) -> OrcParams:
     p.bc_ylo, p.bc_yhi = int(case["bc_ylo"]), int(case["bc_yhi"])
     p.visc_law = int(case["visc_law"])
     p.grad_scheme = int(case.get("grad_scheme", GRAD_ISOTROPIC))
+    p.f_lattice = int(case.get("f_lattice", 9))
     for k in ("rho_l", "rho_g", "nu_l", "nu_g", "sigma", "W", "M", "Gx", "Gy"):
         setattr(p, k, float(case[k]))
     return p
@@ -132,10 +135,10 @@ def lattice():
     return np.array(cx[:]), np.array(cy[:]), w, np.array(opp[:])
 
 
-def feq(phi, ux, uy):
+def feq(phi, ux, uy, qf=9):
     out = np.empty(9)
-    lib().orc_feq(phi, ux, uy, out)
-    return out
+    lib().orc_feq(qf, phi, ux, uy, out)
+    return out[:qf]
 
 
 def geq(p, rho, ux, uy):
@@ -144,10 +147,17 @@ def geq(p, rho, ux, uy):
     return out
 
 
-def fsource(tau_f, dtx, dty, lam, nx, ny):
+def fsource(tau_f, dtx, dty, lam, nx, ny, qf=9):
     out = np.empty(9)
-    lib().orc_fsource(tau_f, dtx, dty, lam, nx, ny, out)
-    return out
+    lib().orc_fsource(qf, tau_f, dtx, dty, lam, nx, ny, out)
+    return out[:qf]
+
+
+def fweights(qf):
+    """Weights of the phase-field lattice with qf velocities (c_0 .. c_{qf-1} of D2Q9)."""
+    out = np.empty(9)
+    lib().orc_fweights(qf, out)
+    return out[:qf]
 
 
 def gforce(tau_g, Fx, Fy, drho, ux, uy, dpx, dpy):
@@ -176,9 +186,10 @@ def closure(case, phi, dpx, dpy, lap, g):
     return dict(zip(CLOSURE_KEYS, out))
 
 
-def normal_local_neq(f, phi, ux, uy, dtx, dty):
-    """Eq. 29 normal at one node; returns (n_x, n_y)."""
+def normal_local_neq(f, phi, ux, uy, dtx, dty, qf=9):
+    """Eq. 29 normal at one node from its qf phase-field populations; returns (n_x, n_y)."""
     out = np.empty(2)
-    lib().orc_normal_local_neq(np.ascontiguousarray(f, dtype=np.float64), phi, ux, uy, dtx,
-                               dty, out)
+    fa = np.zeros(9)
+    fa[:qf] = np.asarray(f, dtype=np.float64)[:qf]
+    lib().orc_normal_local_neq(qf, fa, phi, ux, uy, dtx, dty, out)
     return out

@@ -21,6 +21,7 @@ NU_LINEAR, NU_INVERSE, MU_STEP = 0, 1, 2
 
 PARAM_KEYS = ("rho_l", "rho_g", "nu_l", "nu_g", "sigma", "W", "M", "Gx", "Gy")
 GRAD_ISOTROPIC, GRAD_LOCAL_NEQ = 0, 1   # normal in the phase-field source: Eq. 27 or Eq. 29
+D2Q9, D2Q5 = 9, 5                        # velocity sets of the phase-field lattice
 
 
 def _grid(nx, ny):
@@ -34,7 +35,8 @@ def _base(name, nx, ny, bc_ylo, bc_yhi, visc_law, rho_l, rho_g, nu_l, nu_g, sigm
     return dict(name=name, nx=int(nx), ny=int(ny), bc_ylo=bc_ylo, bc_yhi=bc_yhi,
                 visc_law=visc_law, rho_l=float(rho_l), rho_g=float(rho_g), nu_l=float(nu_l),
                 nu_g=float(nu_g), sigma=float(sigma), W=float(W), M=float(M), Gx=float(Gx),
-                Gy=float(Gy), grad_scheme=GRAD_ISOTROPIC, mask=(0.0, 0.0, 0.0, 0.0, -1.0))
+                Gy=float(Gy), grad_scheme=GRAD_ISOTROPIC, f_lattice=9,
+                mask=(0.0, 0.0, 0.0, 0.0, -1.0))
 
 
 def tanh_profile(d, W):

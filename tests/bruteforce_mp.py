@@ -11,6 +11,7 @@ import mpmath as mp
 mp.mp.dps = 40
 
 W0, WA, WD = mp.mpf(4) / 9, mp.mpf(1) / 9, mp.mpf(1) / 36
+V0, VA = mp.mpf(1) / 3, mp.mpf(1) / 6          # D2Q5 phase-field weights
 HALF = mp.mpf(1) / 2
 PERIODIC, WALL, OPEN = 0, 1, 2
 
@@ -57,7 +58,11 @@ def node_update(prm, P, x, y, grid, f, g, q):
     kap = mp.mpf(3) / 2 * sigma * Wd
     bet = 12 * sigma / Wd
     tau_f = 3 * M + HALF
-    phi = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8]
+    q5 = prm.get("f_lattice", 9) == 5
+    if q5:
+        phi = f[0] + f[1] + f[2] + f[3] + f[4]
+    else:
+        phi = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8]
     assert abs(phi - pc) < mp.mpf(10) ** -35
     rho = phi * (rl - rg) + rg
     mu_phi = 4 * bet * phi * (phi - 1) * (phi - HALF) - kap * lap
@@ -84,20 +89,29 @@ def node_update(prm, P, x, y, grid, f, g, q):
     qn = (phi * ux, phi * uy)
 
     # f equilibrium (Eq. 9) and source (Eq. 11), written per direction
-    fe = [W0 * phi,
-          WA * phi * (1 + 3 * ux), WA * phi * (1 + 3 * uy),
-          WA * phi * (1 - 3 * ux), WA * phi * (1 - 3 * uy),
-          WD * phi * (1 + 3 * (ux + uy)), WD * phi * (1 + 3 * (-ux + uy)),
-          WD * phi * (1 + 3 * (-ux - uy)), WD * phi * (1 + 3 * (ux - uy))]
+    if q5:
+        fe = [V0 * phi,
+              VA * phi * (1 + 3 * ux), VA * phi * (1 + 3 * uy),
+              VA * phi * (1 - 3 * ux), VA * phi * (1 - 3 * uy)]
+    else:
+        fe = [W0 * phi,
+              WA * phi * (1 + 3 * ux), WA * phi * (1 + 3 * uy),
+              WA * phi * (1 - 3 * ux), WA * phi * (1 - 3 * uy),
+              WD * phi * (1 + 3 * (ux + uy)), WD * phi * (1 + 3 * (-ux + uy)),
+              WD * phi * (1 + 3 * (-ux - uy)), WD * phi * (1 + 3 * (ux - uy))]
     if prm.get("grad_scheme", 0) == 1:
         # Eq. 29 in its printed two-step form: |grad phi| from Eq. 29a, then grad phi from
         # Eq. 29b, then n = grad phi / |grad phi|; C is the first moment of f - f^eq plus
         # half the time derivative of phi u.  Where C vanishes the direction is undefined
         # and n is zero.
-        Cx = ((f[1] - fe[1]) - (f[3] - fe[3]) + (f[5] - fe[5]) - (f[6] - fe[6])
-              - (f[7] - fe[7]) + (f[8] - fe[8]) + HALF * Dx)
-        Cy = ((f[2] - fe[2]) - (f[4] - fe[4]) + (f[5] - fe[5]) + (f[6] - fe[6])
-              - (f[7] - fe[7]) - (f[8] - fe[8]) + HALF * Dy)
+        if q5:
+            Cx = (f[1] - fe[1]) - (f[3] - fe[3]) + HALF * Dx
+            Cy = (f[2] - fe[2]) - (f[4] - fe[4]) + HALF * Dy
+        else:
+            Cx = ((f[1] - fe[1]) - (f[3] - fe[3]) + (f[5] - fe[5]) - (f[6] - fe[6])
+                  - (f[7] - fe[7]) + (f[8] - fe[8]) + HALF * Dx)
+            Cy = ((f[2] - fe[2]) - (f[4] - fe[4]) + (f[5] - fe[5]) + (f[6] - fe[6])
+                  - (f[7] - fe[7]) - (f[8] - fe[8]) + HALF * Dy)
         Cm = mp.sqrt(Cx * Cx + Cy * Cy)
         if Cm > mp.mpf("1e-12"):
             A = -tau_f / 3
@@ -110,10 +124,13 @@ def node_update(prm, P, x, y, grid, f, g, q):
     ax = 3 * Dx + lam * nx_
     ay = 3 * Dy + lam * ny_
     cf = 1 - 1 / (2 * tau_f)
-    fs = [mp.mpf(0),
-          cf * WA * ax, cf * WA * ay, -cf * WA * ax, -cf * WA * ay,
-          cf * WD * (ax + ay), cf * WD * (-ax + ay), cf * WD * (-ax - ay), cf * WD * (ax - ay)]
-    fp = [f[i] - (f[i] - fe[i]) / tau_f + fs[i] for i in range(9)]
+    if q5:
+        fs = [mp.mpf(0), cf * VA * ax, cf * VA * ay, -cf * VA * ax, -cf * VA * ay]
+    else:
+        fs = [mp.mpf(0),
+              cf * WA * ax, cf * WA * ay, -cf * WA * ax, -cf * WA * ay,
+              cf * WD * (ax + ay), cf * WD * (-ax + ay), cf * WD * (-ax - ay), cf * WD * (ax - ay)]
+    fp = [f[i] - (f[i] - fe[i]) / tau_f + fs[i] for i in range(len(fe))]
 
     # g equilibrium (Eqs. 16-17) and forcing (Eq. 20), per direction
     def s_ax(cu):
@@ -151,7 +168,8 @@ def step(prm, grid, F, G, Q):
     """F, G: [ny][nx] lists of 9-lists (post-streaming); Q: [ny][nx] of 2-tuples."""
     nx, ny = grid.nx, grid.ny
     P = [[sum(F[y][x]) for x in range(nx)] for y in range(ny)]
-    Fn = [[[None] * 9 for _ in range(nx)] for _ in range(ny)]
+    qf = len(F[0][0])
+    Fn = [[[None] * qf for _ in range(nx)] for _ in range(ny)]
     Gn = [[[None] * 9 for _ in range(nx)] for _ in range(ny)]
     Qn = [[None] * nx for _ in range(ny)]
     for y in range(ny):
@@ -163,20 +181,24 @@ def step(prm, grid, F, G, Q):
                 xd, yd = (x + dx) % nx, y + dy
                 side = grid.lo if yd < 0 else (grid.hi if yd >= ny else None)
                 if side is None or side == PERIODIC:
-                    Fn[yd % ny][xd][i] = fp[i]
+                    if i < qf:
+                        Fn[yd % ny][xd][i] = fp[i]
                     Gn[yd % ny][xd][i] = gp[i]
                 elif side == WALL:
-                    Fn[y][x][o] = fp[i]
+                    if i < qf:
+                        Fn[y][x][o] = fp[i]
                     Gn[y][x][o] = gp[i]
     if grid.hi == OPEN:
         for x in range(nx):
             for i in (4, 7, 8):
-                Fn[ny - 1][x][i] = Fn[ny - 2][x][i]
+                if i < qf:
+                    Fn[ny - 1][x][i] = Fn[ny - 2][x][i]
                 Gn[ny - 1][x][i] = Gn[ny - 2][x][i]
     if grid.lo == OPEN:
         for x in range(nx):
             for i in (2, 5, 6):
-                Fn[0][x][i] = Fn[1][x][i]
+                if i < qf:
+                    Fn[0][x][i] = Fn[1][x][i]
                 Gn[0][x][i] = Gn[1][x][i]
     return Fn, Gn, Qn
 

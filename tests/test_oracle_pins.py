@@ -48,11 +48,27 @@ def test_lattice_isotropy():
 
 # ------------------------------------------------------ moment identities (P1, App. A)
 
+def test_d2q5_lattice():
+    """The D2Q5 phase-field lattice: the rest and axis velocities of Eq. 10, weights summing
+    to one, zero first moment and second moment c_s^2 I (with c_s^2 = 1/3, as the
+    mobility relation Eq. 14 assumes)."""
+    cx, cy, _, _ = _lat()
+    w = O.fweights(5)
+    assert np.allclose(w, [1 / 3, 1 / 6, 1 / 6, 1 / 6, 1 / 6], rtol=0, atol=1e-16)
+    c = np.stack([cx[:5], cy[:5]])
+    assert abs(w.sum() - 1.0) < 1e-15
+    assert np.allclose(c @ w, 0.0, atol=1e-16)
+    assert np.allclose(np.einsum("i,ai,bi->ab", w, c, c), CS2 * np.eye(2), atol=1e-16)
+    assert np.allclose(O.fweights(9), _lat()[2], rtol=0, atol=0)
+
+
+@pytest.mark.parametrize("qf", [9, 5])
 @pytest.mark.parametrize("trial", range(5))
-def test_feq_moments(trial):
+def test_feq_moments(trial, qf):
     cx, cy, w, _ = _lat()
+    cx, cy = cx[:qf], cy[:qf]
     phi, ux, uy = RNG.uniform(-0.2, 1.2), RNG.uniform(-0.1, 0.1), RNG.uniform(-0.1, 0.1)
-    fe = O.feq(phi, ux, uy)
+    fe = O.feq(phi, ux, uy, qf)
     assert abs(fe.sum() - phi) < 1e-15
     assert abs(cx @ fe - phi * ux) < 1e-16 and abs(cy @ fe - phi * uy) < 1e-16
     # second moment phi c_s^2 I (what makes the diffusive flux M grad phi)
@@ -78,15 +94,17 @@ def test_geq_moments_A1(trial):
     assert np.allclose(m3, rho * CS2 * np.einsum("abgt,t->abg", delta, u), atol=tol)
 
 
+@pytest.mark.parametrize("qf", [9, 5])
 @pytest.mark.parametrize("trial", range(5))
-def test_fsource_moments(trial):
+def test_fsource_moments(trial, qf):
     cx, cy, w, _ = _lat()
+    cx, cy = cx[:qf], cy[:qf]
     tau = RNG.uniform(0.55, 2.0)
     D = RNG.uniform(-1e-3, 1e-3, size=2)
     lam = RNG.uniform(0, 0.25)
     ang = RNG.uniform(0, 2 * np.pi)
     n = np.array([np.cos(ang), np.sin(ang)])
-    fs = O.fsource(tau, D[0], D[1], lam, n[0], n[1])
+    fs = O.fsource(tau, D[0], D[1], lam, n[0], n[1], qf)
     k = 1.0 - 1.0 / (2.0 * tau)
     assert abs(fs.sum()) < 1e-17                                # mass is not created
     # first moment (1 - 1/(2 tau)) [d_t(phi u) + c_s^2 lambda n]  (Eq. 11)
@@ -359,7 +377,8 @@ def test_galilean_translation():
                                 (cases.WALL, cases.OPEN), (cases.OPEN, cases.WALL)])
 @pytest.mark.parametrize("law", [cases.NU_LINEAR, cases.MU_STEP])
 @pytest.mark.parametrize("scheme", [cases.GRAD_ISOTROPIC, cases.GRAD_LOCAL_NEQ])
-def test_bruteforce_4x4(bc, law, scheme):
+@pytest.mark.parametrize("qf", [9, 5])
+def test_bruteforce_4x4(bc, law, scheme, qf):
     import mpmath as mp
 
     from tests import bruteforce_mp as B
@@ -367,15 +386,17 @@ def test_bruteforce_4x4(bc, law, scheme):
     c["bc_ylo"], c["bc_yhi"] = bc
     c["visc_law"] = law
     c["grad_scheme"] = scheme
+    c["f_lattice"] = qf
     s = O.OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
     rng = np.random.default_rng(7)
     f = rng.uniform(0.02, 0.1, size=(9, 4, 4))
+    f[qf:] = 0.0
     g = rng.uniform(-1e-3, 1e-3, size=(9, 4, 4))
     q = rng.uniform(-1e-3, 1e-3, size=(2, 4, 4))
     s.set_state(f, g, q)
-    prm = B.to_mp({k: c[k] for k in cases.PARAM_KEYS + ("visc_law", "grad_scheme")})
+    prm = B.to_mp({k: c[k] for k in cases.PARAM_KEYS + ("visc_law", "grad_scheme", "f_lattice")})
     grid = B.Grid(4, 4, *bc)
-    F = [[[mp.mpf(float(f[i, y, x])) for i in range(9)] for x in range(4)] for y in range(4)]
+    F = [[[mp.mpf(float(f[i, y, x])) for i in range(qf)] for x in range(4)] for y in range(4)]
     G = [[[mp.mpf(float(g[i, y, x])) for i in range(9)] for x in range(4)] for y in range(4)]
     Q = [[(mp.mpf(float(q[0, y, x])), mp.mpf(float(q[1, y, x]))) for x in range(4)]
          for y in range(4)]
@@ -387,8 +408,9 @@ def test_bruteforce_4x4(bc, law, scheme):
     mo = s.moments()
     for y in range(4):
         for x in range(4):
-            for i in range(9):
+            for i in range(qf):
                 assert abs(float(F[y][x][i]) - fo[i, y, x]) < 1e-15
+            for i in range(9):
                 assert abs(float(G[y][x][i]) - go[i, y, x]) < 1e-15
             assert abs(float(Q[y][x][0]) - qo[0, y, x]) < 1e-16
             for key in ("phi", "rho", "p", "ux", "uy"):
@@ -456,15 +478,17 @@ def test_eq29_closed_form_equals_printed_two_step_form():
         assert abs(np.hypot(*n) - 1.0) < 1e-14
 
 
-def test_eq29_inverts_the_chapman_enskog_first_moment():
+@pytest.mark.parametrize("qf", [9, 5])
+def test_eq29_inverts_the_chapman_enskog_first_moment(qf):
     """Chapman-Enskog expansion of Eq. 8 with the source of Eq. 11 (M = c_s^2 (tau_f - 1/2))
     gives the first moment of f - f^eq as
         -tau_f c_s^2 grad phi - d_t(phi u)/2 + M lambda grad phi / |grad phi|.
     A node whose f carries exactly that non-equilibrium part must get back the direction of
     the grad phi it was built from (for M lambda < c_s^2 tau_f |grad phi|, the branch Eq. 29a
     takes)."""
-    _, _, w, _ = _lat()
     cx, cy, _, _ = _lat()
+    cx, cy = cx[:qf], cy[:qf]
+    w = O.fweights(qf)
     rng = np.random.default_rng(2929)
     for _ in range(200):
         phi, ux, uy, dtx, dty = _random_node(rng)
@@ -475,8 +499,8 @@ def test_eq29_inverts_the_chapman_enskog_first_moment():
         grad = gmag * np.array([np.cos(ang), np.sin(ang)])
         lam = rng.uniform(0.0, 0.95) * CS2 * tau * gmag / M
         m1 = -tau * CS2 * grad - 0.5 * np.array([dtx, dty]) + M * lam * grad / gmag
-        f = O.feq(phi, ux, uy) + w * (cx * m1[0] + cy * m1[1]) / CS2
-        n = O.normal_local_neq(f, phi, ux, uy, dtx, dty)
+        f = O.feq(phi, ux, uy, qf) + w * (cx * m1[0] + cy * m1[1]) / CS2
+        n = O.normal_local_neq(f, phi, ux, uy, dtx, dty, qf)
         assert np.allclose(n, grad / gmag, rtol=0, atol=1e-9)
 
 
@@ -568,3 +592,59 @@ def test_impact_spreading_power_law():
         ratios.append(d["spread_radius"] / c["D"] / np.sqrt(t))
     C = float(np.mean(ratios))
     assert abs(C / 1.35 - 1) < 0.2
+
+
+# ------------------------------------------------- D2Q5 phase-field lattice (NEXT f2)
+
+def _q5(c):
+    c["f_lattice"] = cases.D2Q5
+    return c
+
+
+@pytest.mark.parametrize("make", [lambda: cases.static_drop(32, 32, R=8),
+                                  lambda: cases.layered_poiseuille(8, 48),
+                                  lambda: cases.droplet_impact(64, 48, D=20, Re=20)])
+def test_d2q5_sum_phi_conserved(make):
+    c = _q5(make())
+    s = O.OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
+    m0 = s.moments()["phi"].sum()
+    s.step(600)
+    m1 = s.moments()["phi"].sum()
+    if c["bc_yhi"] == cases.OPEN:
+        assert abs(m1 - m0) / m0 < 1e-6
+    else:
+        assert abs(m1 - m0) / m0 < 20 * np.finfo(float).eps * 600
+
+
+def test_d2q5_planar_interface_and_laplace_law():
+    """The D2Q5 phase field recovers the same conservative Allen-Cahn equation: a flat
+    interface keeps its tanh profile (Eq. 33) within the same O(W^-2) as with D2Q9, and a
+    static drop obeys the Young-Laplace law within 10 % at W = 4."""
+    dev = {}
+    for qf in (9, 5):
+        c = cases.planar_interface(nx=4, ny=64, W=4.0, ratio=1000.0, sigma=0.01)
+        c["f_lattice"] = qf
+        s = O.OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
+        s.step(3000)
+        dev[qf] = float(np.max(np.abs(s.moments()["phi"] - c["phi0"])))
+    # W = 4 relaxes 5e-3 away from the continuum tanh with either lattice
+    assert dev[9] < 1e-2 and abs(dev[5] - dev[9]) < 0.1 * dev[9]
+    c = _q5(cases.static_drop(64, 64, R=16.0, W=4.0, sigma=0.01))
+    dp, _ = _dp(c, 3000)
+    assert 0.9 < dp * 16.0 / 0.01 < 1.05
+
+
+def test_d2q5_galilean_translation():
+    """Single phase, uniform velocity: the phase profile is advected once around the
+    periodic box and returns to its start within the same bound as D2Q9 (P10)."""
+    res = {}
+    for qf in (9, 5):
+        c = cases.planar_interface(nx=64, ny=8, W=4.0, ratio=1.0, sigma=0.0, ux=0.05)
+        c["phi0"] = cases.tanh_profile(np.minimum(np.arange(64) + 0.5 - 16.0,
+                                                  48.0 - np.arange(64) - 0.5), 4.0)[None, :] \
+            * np.ones((8, 1))
+        c["f_lattice"] = qf
+        s = O.OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
+        s.step(int(64 / 0.05))
+        res[qf] = float(np.max(np.abs(s.moments()["phi"] - c["phi0"])))
+    assert res[5] < 0.05 and res[9] < 0.05
