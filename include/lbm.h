@@ -60,6 +60,13 @@ enum { LBM_VISC_LINEAR = 0, LBM_VISC_INVERSE = 1, LBM_VISC_STEP_MU = 2 };
  * moments always use Eqs. 27-28. */
 enum { LBM_GRAD_ISOTROPIC = 0, LBM_GRAD_LOCAL_NEQ = 1 };
 
+/* velocity set of the phase-field lattice f (Sec. 2.2 admits either): D2Q9 (the paper's
+ * choice, weights 4/9, 1/9, 1/36) or D2Q5 (the rest and the four axis velocities, weights
+ * 1/3 and 1/6, the same c_s^2 = 1/3).  0 selects D2Q9.  The flow lattice g and the
+ * stencils of Eqs. 27-28 are D2Q9 in either case.  Every instance of a context uses the
+ * same set. */
+enum { LBM_LATTICE_D2Q9 = 9, LBM_LATTICE_D2Q5 = 5 };
+
 /* storage of the distributions.  F64: doubles, FP64 arithmetic.  F32 / F16: float / IEEE
  * half holding rest deviations (f_i - w_i phi_w) 2^exp_f, phi_w the order parameter of the
  * node that wrote the slot (kept in an FP32 phi plane), and g_i 2^exp_g; arithmetic in
@@ -91,6 +98,8 @@ typedef struct {
     int32_t exp_f, exp_g;     /* F16 storage exponents (stored value = deviation * 2^exp), or
                                  LBM_EXP_AUTO to derive them from the initial fields;
                                  ignored for F32 and F64 */
+    int32_t f_lattice;        /* LBM_LATTICE_D2Q9 (or 0) or LBM_LATTICE_D2Q5 */
+    int32_t reserved1;
 } lbm_params;
 
 /* Context-wide options. */

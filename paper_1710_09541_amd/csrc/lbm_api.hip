@@ -81,6 +81,7 @@ struct lbm_ctx {
     int64_t step = 0;
     int kernel = LBM_KERNEL_FUSED;
     int tile_rows = 8;
+    int qf = 9;                // velocities of the phase-field lattice
     std::string err;
 };
 
@@ -132,6 +133,8 @@ std::string check_params(const lbm_params& p, int k) {
         return bad("periodic must be set on both y sides or on neither");
     if (p.visc_law < 0 || p.visc_law > 2) return bad("unknown viscosity law");
     if (p.grad_scheme < 0 || p.grad_scheme > 1) return bad("unknown gradient scheme");
+    if (p.f_lattice != 0 && p.f_lattice != LBM_LATTICE_D2Q9 && p.f_lattice != LBM_LATTICE_D2Q5)
+        return bad("unknown phase-field lattice (use 9 or 5)");
     if (!(p.rho_l > 0) || !(p.rho_g > 0)) return bad("densities must be > 0");
     if (!(p.nu_l > 0) || !(p.nu_g > 0)) return bad("viscosities must be > 0");
     if (!(p.W > 0)) return bad("W must be > 0");
@@ -237,6 +240,7 @@ StepArgs step_args(lbm_ctx* c, int src, bool pull, int rows, bool split, void* q
     a.tiles = L.dev;
     a.ntiles = L.count;
     a.tile_rows = rows;
+    a.qf = c->qf;
     a.pull = pull;
     a.split = split;
     a.fsrc = c->f[src];
@@ -463,11 +467,16 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
     if (o.tile_rows != 0 && list_index(o.tile_rows) < 0)
         return fail(nullptr, LBM_ERR_PARAM, "tile_rows must be 0, 4, 8 or 16");
     if (o.check_every < 0) return fail(nullptr, LBM_ERR_PARAM, "check_every must be >= 0");
+    const auto lattice_of = [](const lbm_params& q) {
+        return q.f_lattice == 0 ? (int)LBM_LATTICE_D2Q9 : (int)q.f_lattice;
+    };
     for (int k = 0; k < n_inst; ++k) {
         std::string m = check_params(p[k], k);
         if (!m.empty()) return fail(nullptr, LBM_ERR_PARAM, m);
         if (!phi0[k] || !ux0[k] || !uy0[k])
             return fail(nullptr, LBM_ERR_PARAM, "initial field of an instance is NULL");
+        if (lattice_of(p[k]) != lattice_of(p[0]))
+            return fail(nullptr, LBM_ERR_PARAM, "all instances must use the same phase-field lattice");
     }
 
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
@@ -476,6 +485,7 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
     c->storage = o.storage;
     c->esize = o.storage == STORE_F64 ? 8 : (o.storage == STORE_F32 ? 4 : 2);
     c->qsize = o.storage == STORE_F64 ? 8 : 4;
+    c->qf = lattice_of(p[0]);
     c->inst.resize(n_inst);
     int64_t off_dist = 0, off_q = 0, off_phi = 0, off_mp = 0;
     for (int k = 0; k < n_inst; ++k) {
@@ -593,7 +603,7 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
         if (e == hipSuccess)
             e = hipMemcpy(stage + 2 * n, uy0[k], n * sizeof(double), hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = launch_init(c->storage, c->d_insts, k, c->inst[k].p.nx, c->inst[k].p.ny, stage,
+            e = launch_init(c->storage, c->qf, c->d_insts, k, c->inst[k].p.nx, c->inst[k].p.ny, stage,
                             stage + n, stage + 2 * n, c->f[0], c->g[0], c->q, c->rplane[0],
                             c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

@@ -46,6 +46,7 @@ struct StepArgs {
     const TileDesc* tiles;
     int ntiles;
     int tile_rows;      // 4, 8 or 16
+    int qf;             // velocities of the phase-field lattice: 9 (D2Q9) or 5 (D2Q5)
     bool pull;          // false only for the first step (initial state in streamed form)
     bool split;         // two launches: phi plane, then stencil + collide
     const void* fsrc;
@@ -61,7 +62,7 @@ struct StepArgs {
 
 hipError_t launch_step(int storage, const StepArgs& a);
 hipError_t launch_moments(int storage, const StepArgs& a, double* out);
-hipError_t launch_init(int storage, const InstDev* insts, int inst, int nx, int ny,
+hipError_t launch_init(int storage, int qf, const InstDev* insts, int inst, int nx, int ny,
                        const double* phi0, const double* ux0, const double* uy0, void* f, void* g,
                        void* q, void* rplane, hipStream_t st);
 int reduce_blocks(int64_t n);

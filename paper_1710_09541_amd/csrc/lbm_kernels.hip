@@ -46,6 +46,15 @@ __device__ __forceinline__ C wgt(int i) {
     return i == 0 ? C(4.0 / 9.0) : (i < 5 ? C(1.0 / 9.0) : C(1.0 / 36.0));
 }
 
+// Weights of the phase-field lattice with QF velocities: D2Q9 as above, or D2Q5 (the rest
+// and the four axis velocities c_0..c_4, weights 1/3 and 1/6, the same c_s^2 = 1/3), which
+// Sec. 2.2 admits for the Allen-Cahn lattice.  The flow lattice is always D2Q9.
+template <typename C, int QF>
+__device__ __forceinline__ C wf(int i) {
+    if constexpr (QF == 5) return i == 0 ? C(1.0 / 3.0) : C(1.0 / 6.0);
+    return wgt<C>(i);
+}
+
 // c_i . (a, b) written out per direction: with i known at compile time this folds to one
 // add or none (IEEE arithmetic may not drop a product with a zero component by itself)
 template <typename C>
@@ -210,21 +219,21 @@ __device__ __forceinline__ void pull_local(const InstDev& I, int gy, int lx, int
     }
 }
 
-// phi from the 9 arriving stored values v (unscaled) and, for the rest-deviation formats,
+// phi from the QF arriving stored values v (unscaled) and, for the rest-deviation formats,
 // the phi of their source nodes ref[] and of the node itself (base):
 //   phi = base + sum_i w_i (ref_i - base) + 2^-exp_f sum_i v_i           (Eq. 12)
 // For the rest-deviation formats *res receives the rounding error of the final addition
 // (exact, by Knuth's two-sum): phi + res is the sum before rounding to the phi format.
-template <typename C, bool REF>
+template <typename C, bool REF, int QF>
 __device__ __forceinline__ C phi_of(const C (&v)[9], const C (&ref)[9], C base, C isf,
                                     C* res = nullptr) {
     C s = v[0];
 #pragma unroll
-    for (int i = 1; i < 9; ++i) s += v[i];
+    for (int i = 1; i < QF; ++i) s += v[i];
     if (!REF) return s * isf;
-    C a = wgt<C>(0) * (ref[0] - base);
+    C a = wf<C, QF>(0) * (ref[0] - base);
 #pragma unroll
-    for (int i = 1; i < 9; ++i) a += wgt<C>(i) * (ref[i] - base);
+    for (int i = 1; i < QF; ++i) a += wf<C, QF>(i) * (ref[i] - base);
     const C d = a + s * isf;
     const C phi = base + d;
     if (res) {
@@ -254,7 +263,7 @@ __device__ __forceinline__ double s_exact(int i, double ux, double uy) {
     return wgt<double>(i) * (cu * 3.0 + cu * cu * 4.5 - uu * 1.5);   // Eq. 17
 }
 
-template <int MODE>
+template <int MODE, int QF>
 __device__ __forceinline__ void node_update_f64(const InstDev& I, const double (&f)[9],
                                                 const double (&g)[9], const double (&nb)[9],
                                                 double& qx, double& qy, double (&fo)[9],
@@ -314,25 +323,27 @@ __device__ __forceinline__ void node_update_f64(const InstDev& I, const double (
     qy = puy;
     double fe[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 0; i < QF; ++i) {
         const double cu = CX[i] * ux + CY[i] * uy;
-        fe[i] = wgt<double>(i) * phi * (1.0 + cu * 3.0);                         // Eq. 9
+        fe[i] = wf<double, QF>(i) * phi * (1.0 + cu * 3.0);                      // Eq. 9
     }
     if (I.grad_scheme == GRAD_LOCAL_NEQ) {
         // Eq. 29: n = -C/|C|, C = sum_i c_i (f_i - f_i^eq) + d_t(phi u)/2, the sums taken
         // over i in increasing order
         double cx = f[1] - fe[1];
         cx -= f[3] - fe[3];
-        cx += f[5] - fe[5];
-        cx -= f[6] - fe[6];
-        cx -= f[7] - fe[7];
-        cx += f[8] - fe[8];
         double cy = f[2] - fe[2];
         cy -= f[4] - fe[4];
-        cy += f[5] - fe[5];
-        cy += f[6] - fe[6];
-        cy -= f[7] - fe[7];
-        cy -= f[8] - fe[8];
+        if (QF == 9) {
+            cx += f[5] - fe[5];
+            cx -= f[6] - fe[6];
+            cx -= f[7] - fe[7];
+            cx += f[8] - fe[8];
+            cy += f[5] - fe[5];
+            cy += f[6] - fe[6];
+            cy -= f[7] - fe[7];
+            cy -= f[8] - fe[8];
+        }
         cx += 0.5 * dtx;
         cy += 0.5 * dty;
         const double cm = sqrt(cx * cx + cy * cy);
@@ -347,11 +358,14 @@ __device__ __forceinline__ void node_update_f64(const InstDev& I, const double (
     const double cf = 1.0 - 1.0 / (2.0 * I.tau_f);
     const double cg = 1.0 - 1.0 / (2.0 * tau_g);
 #pragma unroll
+    for (int i = 0; i < QF; ++i) {
+        const double fs = cf * wf<double, QF>(i) * (CX[i] * vx + CY[i] * vy);   // Eq. 11
+        fo[i] = f[i] - (f[i] - fe[i]) / I.tau_f + fs;                            // Eq. 8
+    }
+#pragma unroll
     for (int i = 0; i < 9; ++i) {
         const double w = wgt<double>(i);
         const double cu = CX[i] * ux + CY[i] * uy;
-        const double fs = cf * w * (CX[i] * vx + CY[i] * vy);                    // Eq. 11
-        fo[i] = f[i] - (f[i] - fe[i]) / I.tau_f + fs;                            // Eq. 8
         const double ge = (i == 0 ? pr * 3.0 * (w - 1.0) : pr * 3.0 * w) + rho * s_exact(i, ux, uy);
         const double cF = CX[i] * Fx + CY[i] * Fy;
         const double cgp = CX[i] * dpx + CY[i] * dpy;
@@ -396,7 +410,7 @@ __device__ __forceinline__ float geq_ref(int i, float A, float B, float ux, floa
 // Writes the collided e_i into fo, the g deviations g*_i - g^eq_i(published moments) into
 // go and the published p_w, u_w into pw, or the moments into mom.  FIRST: the state is the
 // initial one, f = f^eq(phi0, u0) and g = g^eq(p = 0, u0) at every node.
-template <int MODE, bool FIRST>
+template <int MODE, bool FIRST, int QF>
 __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&f)[9],
                                                 const float (&eg)[9], const float (&gs)[9],
                                                 float phi, float pE, float pN, float pW,
@@ -493,8 +507,11 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
             cx = k * Fx;
             cy = k * Fy;
         } else {
-            const C ex = ((f[1] - f[3]) + (f[5] - f[7])) + (f[8] - f[6]);
-            const C ey = ((f[2] - f[4]) + (f[5] - f[7])) + (f[6] - f[8]);
+            C ex = f[1] - f[3], ey = f[2] - f[4];
+            if (QF == 9) {
+                ex = (ex + (f[5] - f[7])) + (f[8] - f[6]);
+                ey = (ey + (f[5] - f[7])) + (f[6] - f[8]);
+            }
             cx = ex - C(0.5) * (phi * cux + qx);
             cy = ey - C(0.5) * (phi * cuy + qy);
         }
@@ -517,15 +534,15 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
     const C ay = C(3) * Dy + lam * ny_;
     const C phi3 = C(3) * phi;
 #pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        const C w = wgt<C>(i);
+    for (int i = 1; i < QF; ++i) {
+        const C w = wf<C, QF>(i);
         const C feq = w * phi3 * dotc<C>(i, cux, cuy);
         const C src = cf * w * dotc<C>(i, ax, ay);
         fo[i] = f[i] - (f[i] - feq) * itf + src;
     }
     C t = fo[1];
 #pragma unroll
-    for (int i = 2; i < 9; ++i) t += fo[i];
+    for (int i = 2; i < QF; ++i) t += fo[i];
     fo[0] = res - t;
 
     // g collision (Eqs. 15-17, 20) on deviations from the published equilibrium gw:
@@ -583,7 +600,7 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
 // q: FP64 format, phi u of the previous step (2 planes, updated in place).
 // msrc / mdst: reduced formats, the planes phi_w, p_w, ux_w, uy_w of the previous step
 // (read) and of this step (written).
-template <typename S, int K, bool PULL, int MODE, bool RING_FROM_PLANE, bool INTERIOR>
+template <typename S, int K, bool PULL, int MODE, bool RING_FROM_PLANE, bool INTERIOR, int QF>
 __device__ __forceinline__ void step_tile(
     const InstDev& I, const TileDesc& T, const S* __restrict__ fsrc,
     const S* __restrict__ gsrc, S* __restrict__ fdst, S* __restrict__ gdst,
@@ -656,7 +673,7 @@ __device__ __forceinline__ void step_tile(
             int o[9], src[9];
             pull_offsets<PULL, INTERIOR>(I, x, y, o, src);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) f[k][i] = Store<S>::get(fb, o[i]);
+            for (int i = 0; i < QF; ++i) f[k][i] = Store<S>::get(fb, o[i]);
 #pragma unroll
             for (int i = 0; i < 9; ++i) g[k][i] = Store<S>::get(gb, o[i]);
         }
@@ -689,7 +706,7 @@ __device__ __forceinline__ void step_tile(
             int o[9], src[9];
             pull_offsets<PULL, INTERIOR>(I, rgx, rgy, o, src);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) rfv[i] = Store<S>::get(fb, o[i]);
+            for (int i = 0; i < QF; ++i) rfv[i] = Store<S>::get(fb, o[i]);
         }
     }
     if (REF) __syncthreads();
@@ -706,10 +723,10 @@ __device__ __forceinline__ void step_tile(
                 int r[9], dir[9];
                 pull_local<PULL, INTERIOR>(I, T.y0 + yl, lx, yl, r, dir);
 #pragma unroll
-                for (int i = 0; i < 9; ++i) ref[i] = sw[r[i]].x;
+                for (int i = 0; i < QF; ++i) ref[i] = sw[r[i]].x;
                 base = sw[(yl + 2) * RW + lx + 2].x;
             }
-            sphi[(yl + 1) * LW + lx + 1] = phi_of<C, REF>(f[k], ref, base, isf, &res[k]);
+            sphi[(yl + 1) * LW + lx + 1] = phi_of<C, REF, QF>(f[k], ref, base, isf, &res[k]);
         }
     }
     if (on_ring) {
@@ -726,10 +743,10 @@ __device__ __forceinline__ void step_tile(
                 int r[9], dir[9];
                 pull_local<PULL, INTERIOR>(I, gy, rx, lyl, r, dir);
 #pragma unroll
-                for (int i = 0; i < 9; ++i) ref[i] = sw[r[i]].x;
+                for (int i = 0; i < QF; ++i) ref[i] = sw[r[i]].x;
                 base = sw[(lyl + 2) * RW + rx + 2].x;
             }
-            v = phi_of<C, REF>(rfv, ref, base, isf);
+            v = phi_of<C, REF, QF>(rfv, ref, base, isf);
         }
         sphi[(ry + 1) * LW + rx + 1] = v;
     }
@@ -757,17 +774,17 @@ __device__ __forceinline__ void step_tile(
             for (int i = 0; i < 9; ++i) {
                 const float4 q4 = sq[r[i]];
                 const float2 q2 = sw[r[i]];
-                fd[i] = __builtin_fmaf(wgt<float>(i), q2.x - phi, f[k][i] * isf);
+                if (i < QF) fd[i] = __builtin_fmaf(wf<float, QF>(i), q2.x - phi, f[k][i] * isf);
                 eg[i] = g[k][i] * isg;
                 gs[i] = geq_ref(dir[i], q4.x, q4.y, q4.z, q4.w, q2.y);
             }
             const int me = (yl + 2) * RW + lx + 2;
             const float qx = sw[me].x * sq[me].z, qy = sw[me].x * sq[me].w;
-            node_update_ref<MODE, !PULL>(I, fd, eg, gs, phi, r1[2], r2[1], r1[0], r0[1], r2[2], r2[0],
+            node_update_ref<MODE, !PULL, QF>(I, fd, eg, gs, phi, r1[2], r2[1], r1[0], r0[1], r2[2], r2[0],
                                   r0[0], r0[2], res[k], qx, qy, fo, go, pw, mom);
             if (MODE == MODE_STEP) {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) Store<S>::put(fo_b, i * plane + self, fo[i] * sf);
+                for (int i = 0; i < QF; ++i) Store<S>::put(fo_b, i * plane + self, fo[i] * sf);
 #pragma unroll
                 for (int i = 0; i < 9; ++i) Store<S>::put(go_b, i * plane + self, go[i] * sgs);
                 float* mo = mdst + I.off_mp;
@@ -781,10 +798,10 @@ __device__ __forceinline__ void step_tile(
             double qx = qb[self], qy = qb[plane + self];
             const double nb[9] = {phi, r1[2], r2[1], r1[0], r0[1], r2[2], r2[0], r0[0], r0[2]};
             double fo[9], go[9];
-            node_update_f64<MODE>(I, f[k], g[k], nb, qx, qy, fo, go, mom);
+            node_update_f64<MODE, QF>(I, f[k], g[k], nb, qx, qy, fo, go, mom);
             if (MODE == MODE_STEP) {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) Store<S>::put(fo_b, i * plane + self, fo[i]);
+                for (int i = 0; i < QF; ++i) Store<S>::put(fo_b, i * plane + self, fo[i]);
 #pragma unroll
                 for (int i = 0; i < 9; ++i) Store<S>::put(go_b, i * plane + self, go[i]);
                 qb[self] = qx;
@@ -803,7 +820,7 @@ __device__ __forceinline__ void step_tile(
 
 // A tile whose staged region (two nodes around it) lies inside the grid runs a copy of the
 // body without wrap and boundary logic; edge tiles take the general path.
-template <typename S, int K, bool PULL, int MODE, bool RING_FROM_PLANE>
+template <typename S, int K, bool PULL, int MODE, bool RING_FROM_PLANE, int QF>
 __global__ __launch_bounds__(BLOCK) void k_step(
     const InstDev* __restrict__ insts, const TileDesc* __restrict__ tiles, int ntiles,
     int per_xcd, const S* __restrict__ fsrc, const S* __restrict__ gsrc, S* __restrict__ fdst,
@@ -826,11 +843,11 @@ __global__ __launch_bounds__(BLOCK) void k_step(
     const bool interior = PULL && T.x0 >= 2 && T.x0 + TILE_X + 2 <= I.nx && T.y0 >= 2 &&
                           T.y0 + TY + 2 <= I.ny;
     if (interior)
-        step_tile<S, K, PULL, MODE, RING_FROM_PLANE, true>(I, T, fsrc, gsrc, fdst, gdst, q,
+        step_tile<S, K, PULL, MODE, RING_FROM_PLANE, true, QF>(I, T, fsrc, gsrc, fdst, gdst, q,
                                                            phiplane, msrc, mdst, mom_out, sphi,
                                                            sq, sw);
     else
-        step_tile<S, K, PULL, MODE, RING_FROM_PLANE, false>(I, T, fsrc, gsrc, fdst, gdst, q,
+        step_tile<S, K, PULL, MODE, RING_FROM_PLANE, false, QF>(I, T, fsrc, gsrc, fdst, gdst, q,
                                                             phiplane, msrc, mdst, mom_out, sphi,
                                                             sq, sw);
 }
@@ -838,7 +855,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(
 // ------------------------------------------------------------------ split step: phi plane
 // First half of the two-launch step: phi (Eq. 12) of every node from the pulled f, with the
 // same arithmetic as the fused kernel (source-node phi read from memory, not LDS).
-template <typename S, int K>
+template <typename S, int K, int QF>
 __global__ __launch_bounds__(BLOCK) void k_phi_plane(
     const InstDev* __restrict__ insts, const TileDesc* __restrict__ tiles, int ntiles,
     int per_xcd, const S* __restrict__ fsrc, const float* __restrict__ msrc,
@@ -866,13 +883,13 @@ __global__ __launch_bounds__(BLOCK) void k_phi_plane(
             pull_offsets<true>(I, x, y, o, src);
             C v[9], ref[9], base = C(0);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) v[i] = Store<S>::get(fb, o[i]);
+            for (int i = 0; i < QF; ++i) v[i] = Store<S>::get(fb, o[i]);
             if (REF) {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) ref[i] = rb[src[i]];
+                for (int i = 0; i < QF; ++i) ref[i] = rb[src[i]];
                 base = rb[y * I.pitch + x];
             }
-            phiplane[I.off_phi + y * I.pitch + x] = phi_of<C, REF>(v, ref, base, isf);
+            phiplane[I.off_phi + y * I.pitch + x] = phi_of<C, REF, QF>(v, ref, base, isf);
         }
     }
 }
@@ -890,7 +907,7 @@ __device__ __forceinline__ double init_rho(double ph, double drho, double rho_g)
 // f = f^eq(phi0, u0) (Eq. 9), g = g^eq(p = 0, u0) with rho(phi0) (Eq. 16), phi u = phi0 u0,
 // in the storage format, already in streamed form (FP64: q planes; reduced formats: the
 // planes phi_w, p_w = 0, u_w and deviations from them).
-template <typename S>
+template <typename S, int QF>
 __global__ __launch_bounds__(BLOCK) void k_init(const InstDev* __restrict__ insts, int inst,
                                                 const double* __restrict__ phi0,
                                                 const double* __restrict__ ux0,
@@ -913,18 +930,24 @@ __global__ __launch_bounds__(BLOCK) void k_init(const InstDev* __restrict__ inst
     const float phw = (float)ph, uxw = (float)ux, uyw = (float)uy;
     const RefTerms R = ref_terms(I, phw, 0.0f, uxw, uyw);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const double w = wgt<double>(i);
+    for (int i = 0; i < QF; ++i) {
+        const double w = wf<double, QF>(i);
         const double cu = CX[i] * ux + CY[i] * uy;
         const double fe = init_feq(w, ph, cu);
-        const double ge = rho * s_exact(i, ux, uy);   // p = 0
         if (REF) {
             const double ed = fe - w * (double)phw;
-            const double eg = ge - (double)geq_ref(i, R.A, R.B, uxw, uyw, R.H);
             Store<S>::put(fb, i * plane + self, (float)ed * (float)I.scale_f);
-            Store<S>::put(gb, i * plane + self, (float)eg * (float)I.scale_g);
         } else {
             Store<S>::put(fb, i * plane + self, (C)fe);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const double ge = rho * s_exact(i, ux, uy);   // p = 0
+        if (REF) {
+            const double eg = ge - (double)geq_ref(i, R.A, R.B, uxw, uyw, R.H);
+            Store<S>::put(gb, i * plane + self, (float)eg * (float)I.scale_g);
+        } else {
             Store<S>::put(gb, i * plane + self, (C)ge);
         }
     }
@@ -948,7 +971,7 @@ inline int grid_for(int ntiles, int& per_xcd) {
     return per_xcd * NXCD;
 }
 
-template <typename S, int K>
+template <typename S, int K, int QF>
 hipError_t step_k(const StepArgs& a) {
     using C = typename Store<S>::C;
     int per;
@@ -962,89 +985,106 @@ hipError_t step_k(const StepArgs& a) {
     const float* rs = (const float*)a.rsrc;
     float* rd = (float*)a.rdst;
     if (!a.pull) {
-        k_step<S, K, false, MODE_STEP, false><<<grid, BLOCK, 0, a.stream>>>(
+        k_step<S, K, false, MODE_STEP, false, QF><<<grid, BLOCK, 0, a.stream>>>(
             a.insts, a.tiles, a.ntiles, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
     } else if (a.split) {
-        k_phi_plane<S, K><<<grid, BLOCK, 0, a.stream>>>(a.insts, a.tiles, a.ntiles, per, fs, rs,
-                                                        ph);
-        k_step<S, K, true, MODE_STEP, true><<<grid, BLOCK, 0, a.stream>>>(
+        k_phi_plane<S, K, QF><<<grid, BLOCK, 0, a.stream>>>(a.insts, a.tiles, a.ntiles, per, fs,
+                                                            rs, ph);
+        k_step<S, K, true, MODE_STEP, true, QF><<<grid, BLOCK, 0, a.stream>>>(
             a.insts, a.tiles, a.ntiles, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
     } else {
-        k_step<S, K, true, MODE_STEP, false><<<grid, BLOCK, 0, a.stream>>>(
+        k_step<S, K, true, MODE_STEP, false, QF><<<grid, BLOCK, 0, a.stream>>>(
             a.insts, a.tiles, a.ntiles, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
     }
     return hipGetLastError();
 }
 
-template <typename S>
+template <typename S, int QF>
 hipError_t step_s(const StepArgs& a) {
     switch (a.tile_rows) {
-        case 4: return step_k<S, 1>(a);
-        case 8: return step_k<S, 2>(a);
-        case 16: return step_k<S, 4>(a);
+        case 4: return step_k<S, 1, QF>(a);
+        case 8: return step_k<S, 2, QF>(a);
+        case 16: return step_k<S, 4, QF>(a);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <typename S>
+template <typename S, int QF>
 hipError_t moments_s(const StepArgs& a, double* out) {
-    using C = typename Store<S>::C;
     int per;
     const int grid = grid_for(a.ntiles, per);
     const S* fs = (const S*)a.fsrc;
     const S* gs = (const S*)a.gsrc;
     const float* rs = (const float*)a.rsrc;
     if (a.pull)
-        k_step<S, 1, true, MODE_MOMENTS, false><<<grid, BLOCK, 0, a.stream>>>(
+        k_step<S, 1, true, MODE_MOMENTS, false, QF><<<grid, BLOCK, 0, a.stream>>>(
             a.insts, a.tiles, a.ntiles, per, fs, gs, nullptr, nullptr, (double*)a.q, nullptr,
             rs, nullptr, out);
     else
-        k_step<S, 1, false, MODE_MOMENTS, false><<<grid, BLOCK, 0, a.stream>>>(
+        k_step<S, 1, false, MODE_MOMENTS, false, QF><<<grid, BLOCK, 0, a.stream>>>(
             a.insts, a.tiles, a.ntiles, per, fs, gs, nullptr, nullptr, (double*)a.q, nullptr,
             rs, nullptr, out);
+    return hipGetLastError();
+}
+
+template <typename S, int QF>
+hipError_t init_s(const InstDev* insts, int inst, int nx, int ny, const double* phi0,
+                  const double* ux0, const double* uy0, void* f, void* g, void* q, void* rplane,
+                  hipStream_t st) {
+    dim3 grid((nx + TILE_X - 1) / TILE_X, (ny + 3) / 4);
+    k_init<S, QF><<<grid, BLOCK, 0, st>>>(insts, inst, phi0, ux0, uy0, (S*)f, (S*)g,
+                                          (double*)q, (float*)rplane);
     return hipGetLastError();
 }
 
 template <typename S>
-hipError_t init_s(const InstDev* insts, int inst, int nx, int ny, const double* phi0,
+hipError_t step_q(const StepArgs& a) {
+    return a.qf == 5 ? step_s<S, 5>(a) : step_s<S, 9>(a);
+}
+template <typename S>
+hipError_t moments_q(const StepArgs& a, double* out) {
+    return a.qf == 5 ? moments_s<S, 5>(a, out) : moments_s<S, 9>(a, out);
+}
+template <typename S>
+hipError_t init_q(int qf, const InstDev* insts, int inst, int nx, int ny, const double* phi0,
                   const double* ux0, const double* uy0, void* f, void* g, void* q, void* rplane,
                   hipStream_t st) {
-    using C = typename Store<S>::C;
-    dim3 grid((nx + TILE_X - 1) / TILE_X, (ny + 3) / 4);
-    k_init<S><<<grid, BLOCK, 0, st>>>(insts, inst, phi0, ux0, uy0, (S*)f, (S*)g, (double*)q,
-                                      (float*)rplane);
-    return hipGetLastError();
+    return qf == 5 ? init_s<S, 5>(insts, inst, nx, ny, phi0, ux0, uy0, f, g, q, rplane, st)
+                   : init_s<S, 9>(insts, inst, nx, ny, phi0, ux0, uy0, f, g, q, rplane, st);
 }
 }  // namespace
 
 hipError_t launch_step(int storage, const StepArgs& a) {
+    if (a.qf != 5 && a.qf != 9) return hipErrorInvalidValue;
     switch (storage) {
-        case STORE_F64: return step_s<double>(a);
-        case STORE_F32: return step_s<float>(a);
-        case STORE_F16: return step_s<_Float16>(a);
+        case STORE_F64: return step_q<double>(a);
+        case STORE_F32: return step_q<float>(a);
+        case STORE_F16: return step_q<_Float16>(a);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_moments(int storage, const StepArgs& a, double* out) {
+    if (a.qf != 5 && a.qf != 9) return hipErrorInvalidValue;
     switch (storage) {
-        case STORE_F64: return moments_s<double>(a, out);
-        case STORE_F32: return moments_s<float>(a, out);
-        case STORE_F16: return moments_s<_Float16>(a, out);
+        case STORE_F64: return moments_q<double>(a, out);
+        case STORE_F32: return moments_q<float>(a, out);
+        case STORE_F16: return moments_q<_Float16>(a, out);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_init(int storage, const InstDev* insts, int inst, int nx, int ny,
+hipError_t launch_init(int storage, int qf, const InstDev* insts, int inst, int nx, int ny,
                        const double* phi0, const double* ux0, const double* uy0, void* f, void* g,
                        void* q, void* rplane, hipStream_t st) {
+    if (qf != 5 && qf != 9) return hipErrorInvalidValue;
     switch (storage) {
         case STORE_F64:
-            return init_s<double>(insts, inst, nx, ny, phi0, ux0, uy0, f, g, q, rplane, st);
+            return init_q<double>(qf, insts, inst, nx, ny, phi0, ux0, uy0, f, g, q, rplane, st);
         case STORE_F32:
-            return init_s<float>(insts, inst, nx, ny, phi0, ux0, uy0, f, g, q, rplane, st);
+            return init_q<float>(qf, insts, inst, nx, ny, phi0, ux0, uy0, f, g, q, rplane, st);
         case STORE_F16:
-            return init_s<_Float16>(insts, inst, nx, ny, phi0, ux0, uy0, f, g, q, rplane, st);
+            return init_q<_Float16>(qf, insts, inst, nx, ny, phi0, ux0, uy0, f, g, q, rplane, st);
         default: return hipErrorInvalidValue;
     }
 }

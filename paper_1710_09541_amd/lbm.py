@@ -18,6 +18,8 @@ LBM_BC_PERIODIC, LBM_BC_WALL, LBM_BC_OPEN = 0, 1, 2
 LBM_VISC_LINEAR, LBM_VISC_INVERSE, LBM_VISC_STEP_MU = 0, 1, 2
 LBM_STORE_F64, LBM_STORE_F32, LBM_STORE_F16 = 0, 1, 2
 LBM_KERNEL_AUTO, LBM_KERNEL_FUSED, LBM_KERNEL_SPLIT = 0, 1, 2
+LBM_GRAD_ISOTROPIC, LBM_GRAD_LOCAL_NEQ = 0, 1
+LBM_LATTICE_D2Q9, LBM_LATTICE_D2Q5 = 9, 5
 LBM_EXP_AUTO = -1000
 
 STORAGE = {"f64": LBM_STORE_F64, "f32": LBM_STORE_F32, "f16": LBM_STORE_F16}
@@ -35,7 +37,8 @@ class lbm_params(C.Structure):
                 ("nu_l", C.c_double), ("nu_g", C.c_double),
                 ("sigma", C.c_double), ("W", C.c_double), ("M", C.c_double),
                 ("Gx", C.c_double), ("Gy", C.c_double),
-                ("exp_f", C.c_int32), ("exp_g", C.c_int32)]
+                ("exp_f", C.c_int32), ("exp_g", C.c_int32),
+                ("f_lattice", C.c_int32), ("reserved1", C.c_int32)]
 
 
 class lbm_options(C.Structure):
@@ -113,6 +116,7 @@ def make_params(case, exp_f=LBM_EXP_AUTO, exp_g=LBM_EXP_AUTO) -> lbm_params:
     for k in ("rho_l", "rho_g", "nu_l", "nu_g", "sigma", "W", "M", "Gx", "Gy"):
         setattr(p, k, float(case[k]))
     p.exp_f, p.exp_g = int(exp_f), int(exp_g)
+    p.f_lattice = int(case.get("f_lattice", 9))
     return p
 
 

@@ -61,7 +61,7 @@ def _init(case, **kw):
 
 
 @pytest.mark.parametrize("key,value", [("nx", 2), ("ny", 1), ("rho_g", 0.0), ("W", 0.0),
-                                       ("M", -1.0), ("nu_l", 0.0), ("visc_law", 9), ("grad_scheme", 2),
+                                       ("M", -1.0), ("nu_l", 0.0), ("visc_law", 9), ("grad_scheme", 2), ("f_lattice", 7),
                                        ("sigma", -1.0), ("Gx", float("nan"))])
 def test_invalid_parameters_rejected_before_device(key, value):
     c = cases.static_drop(16, 16, R=4)
@@ -106,3 +106,14 @@ def test_no_device_reported_as_device_error():
     with pytest.raises(lbm.LbmError) as e:
         _init(c)
     assert e.value.code == lbm.LBM_ERR_DEVICE
+
+
+def test_mixed_phase_field_lattices_rejected():
+    a = cases.static_drop(16, 16, R=4)
+    b = cases.static_drop(16, 16, R=4)
+    b["f_lattice"] = cases.D2Q5
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_init([lbm.make_params(a), lbm.make_params(b)], lbm.make_options(),
+                     [a["phi0"], b["phi0"]], [a["ux0"], b["ux0"]], [a["uy0"], b["uy0"]])
+    assert e.value.code == lbm.LBM_ERR_PARAM
+    assert "lattice" in lbm.lbm_last_error()
