@@ -15,7 +15,8 @@ same device and reported next to it, each with its error against the FP64 CPU or
   step viscosity, density ratio 1000), where the stated tolerances apply.
 
 Also timed: the same spinodal at 4096 x 4096 (working set far above the 256 MB last-level
-cache, so the bandwidth is HBM's) and a batch of 256 independent instances of uneven size.
+cache, so the bandwidth is HBM's), a batch of 256 independent instances of uneven size, and
+the spinodal with the D2Q5 phase-field lattice (5 instead of 9 f populations).
 
 Prints ONE JSON line.  Inputs are resident in device memory before the timed region;
 timing uses HIP events recorded on the stream the library launches on.
@@ -38,6 +39,12 @@ PEAK_HBM_GBS = 8000.0
 # written once, plus the per-node state beside them read and written once: FP64 phi u of
 # the previous step (2 doubles); reduced formats the FP32 planes phi_w, p_w, ux_w, uy_w
 ALG_BYTES = {"f64": 36 * 8 + 4 * 8, "f32": 36 * 4 + 8 * 4, "f16": 36 * 2 + 8 * 4}
+ESIZE = {"f64": 8, "f32": 4, "f16": 2}
+
+
+def alg_bytes(storage, qf=9):
+    """Algorithmic bytes per lattice update with a phase-field lattice of qf velocities."""
+    return 2 * (qf + 9) * ESIZE[storage] + 32
 TOL = {"f64": 1e-12, "f32": 1e-5, "f16": 1e-3}
 KERNEL_SRC = os.path.join(ROOT, "paper_1710_09541_amd", "csrc", "lbm_kernels.hip")
 
@@ -106,12 +113,13 @@ def time_gpu(cs, storage, steps, warmup, kernel, tile_rows):
 
 def measure(cs, storage, steps, warmup, kernel="auto", tile_rows=0):
     nodes = sum(c["nx"] * c["ny"] for c in cs)
+    qf = cs[0].get("f_lattice", 9)
     ms, info = time_gpu(cs, storage, steps, warmup, kernel, tile_rows)
     per_launch_s = ms / 1e3 / steps
-    ach = ALG_BYTES[storage] * nodes / per_launch_s / 1e9
+    ach = alg_bytes(storage, qf) * nodes / per_launch_s / 1e9
     return {"mlups": nodes * steps / (ms / 1e3) / 1e6, "ms_per_step": ms / steps,
-            "kernel": info["kernel"], "tile_rows": info["tile_rows"],
-            "alg_bytes_per_lu": ALG_BYTES[storage], "achieved_gbs": ach,
+            "kernel": info["kernel"], "tile_rows": info["tile_rows"], "f_lattice": qf,
+            "alg_bytes_per_lu": alg_bytes(storage, qf), "achieved_gbs": ach,
             "frac_hbm_peak": ach / PEAK_HBM_GBS, "nodes": nodes, "steps": steps}
 
 
@@ -251,6 +259,13 @@ def main():
             extra["spinodal4096_" + st] = r
             log("4096^2 %s: %.1f MLUPS, %.0f GB/s algorithmic" % (st, r["mlups"], r["achieved_gbs"]))
         del big
+        q5, _ = workload("spinodal1024")
+        q5[0]["f_lattice"] = 5
+        for st in ("f32", "f64", "f16"):
+            r = measure(q5, st, args.steps // 4, args.warmup)
+            extra["spinodal1024_d2q5_" + st] = r
+            log("1024^2 D2Q5 %s: %.1f MLUPS, %.0f GB/s algorithmic" % (st, r["mlups"],
+                                                                       r["achieved_gbs"]))
         bcs, bdesc = workload("batch256")
         for st in ("f32", "f64"):
             r = measure(bcs, st, 200, 10)
