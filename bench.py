@@ -118,7 +118,8 @@ def measure(cs, storage, steps, warmup, kernel="auto", tile_rows=0):
     per_launch_s = ms / 1e3 / steps
     ach = alg_bytes(storage, qf) * nodes / per_launch_s / 1e9
     return {"mlups": nodes * steps / (ms / 1e3) / 1e6, "ms_per_step": ms / steps,
-            "kernel": info["kernel"], "tile_rows": info["tile_rows"], "f_lattice": qf,
+            "kernel": info["kernel"], "tile_rows": info["tile_rows"], "stores": info["stores"],
+            "f_lattice": qf,
             "alg_bytes_per_lu": alg_bytes(storage, qf), "achieved_gbs": ach,
             "frac_hbm_peak": ach / PEAK_HBM_GBS, "nodes": nodes, "steps": steps}
 
@@ -290,7 +291,8 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32", "f16": "f32"}[args.storage],
         "data": "synthetic",
         "config": {"workload": desc, "storage": args.storage, "nodes": nodes,
-                   "kernel": kname, "tile_rows": main_r["tile_rows"]},
+                   "kernel": kname, "tile_rows": main_r["tile_rows"],
+                   "stores": main_r["stores"]},
         "roofline": {"bound": "hbm", "achieved": round(main_r["achieved_gbs"], 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(main_r["frac_hbm_peak"], 4),

@@ -73,6 +73,12 @@ enum { LBM_LATTICE_D2Q9 = 9, LBM_LATTICE_D2Q5 = 5 };
  * FP32, with phi-to-rho and the velocity and pressure moments (Eqs. 13, 22) in FP64. */
 enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16 = 2 };
 
+/* population stores of the step: AUTO lets the autotuner choose; CACHED are ordinary
+ * stores; STREAMING are non-temporal stores that do not allocate in the caches (they pay
+ * when the working set exceeds the last-level cache, 256 MB on MI355X, and cost when it
+ * fits).  Results are bitwise identical either way. */
+enum { LBM_STORES_AUTO = 0, LBM_STORES_CACHED = 1, LBM_STORES_STREAMING = 2 };
+
 /* kernel choice for the step */
 enum {
     LBM_KERNEL_AUTO = 0,  /* the autotuner picks */
@@ -110,7 +116,8 @@ typedef struct {
     int32_t use_graph;        /* 1: lbm_step replays captured HIP graphs of two steps */
     int32_t check_every;      /* > 0: every that many steps lbm_step checks for non-finite
                                  values and returns LBM_ERR_NONFINITE (synchronises) */
-    int32_t reserved[3];
+    int32_t stores;           /* LBM_STORES_* */
+    int32_t reserved[2];
 } lbm_options;
 
 /* Integral diagnostics of one instance, FP64 accumulation in a fixed order. */
@@ -167,8 +174,11 @@ int lbm_get_state(lbm_ctx* c, void* buf, size_t* bytes);
  * storage.  Synchronises. */
 int lbm_set_state(lbm_ctx* c, const void* buf, size_t bytes);
 
-/* Number of steps taken; the tile rows and kernel the context runs with. */
-int lbm_info(const lbm_ctx* c, int64_t* step, int32_t* kernel, int32_t* tile_rows);
+/* Number of steps taken; the kernel (LBM_KERNEL_FUSED / SPLIT), tile rows and population
+ * stores (LBM_STORES_CACHED / STREAMING) the context runs with.  Any pointer may be NULL;
+ * LBM_ERR_PARAM if c is NULL. */
+int lbm_info(const lbm_ctx* c, int64_t* step, int32_t* kernel, int32_t* tile_rows,
+             int32_t* stores);
 
 /* Message of the last error of c, or of the calling thread if c is NULL. */
 const char* lbm_last_error(const lbm_ctx* c);

@@ -82,6 +82,7 @@ struct lbm_ctx {
     int kernel = LBM_KERNEL_FUSED;
     int tile_rows = 8;
     int qf = 9;                // velocities of the phase-field lattice
+    bool nt_store = false;     // non-temporal population stores
     std::string err;
 };
 
@@ -241,6 +242,7 @@ StepArgs step_args(lbm_ctx* c, int src, bool pull, int rows, bool split, void* q
     a.ntiles = L.count;
     a.tile_rows = rows;
     a.qf = c->qf;
+    a.nt_store = false;
     a.pull = pull;
     a.split = split;
     a.fsrc = c->f[src];
@@ -260,7 +262,10 @@ int launch_one(lbm_ctx* c, hipStream_t st) {
     if (c->streamed)
         a = step_args(c, c->cur, false, 4, false, c->q);
     else
+    {
         a = step_args(c, c->cur, true, c->tile_rows, c->kernel == LBM_KERNEL_SPLIT, c->q);
+        a.nt_store = c->nt_store;
+    }
     a.stream = st;
     hipError_t e = launch_step(c->storage, a);
     if (e != hipSuccess) return hip_fail(c, e, "step launch");
@@ -353,20 +358,27 @@ int check_finite(lbm_ctx* c) {
 int autotune(lbm_ctx* c) {
     struct Cand {
         int kernel, rows;
+        bool nt;
     };
     std::vector<Cand> cands;
     const bool want_fused = c->opt.kernel != LBM_KERNEL_SPLIT;
     const bool want_split = c->opt.kernel != LBM_KERNEL_FUSED;
+    const bool want_cached = c->opt.stores != LBM_STORES_STREAMING;
+    const bool want_nt = c->opt.stores != LBM_STORES_CACHED;
     const int rows_opts[3] = {4, 8, 16};
     for (int r : rows_opts) {
         if (c->opt.tile_rows && c->opt.tile_rows != r) continue;
         if (c->storage == STORE_F64 && r == 16) continue;  // 16 rows of doubles spill
-        if (want_fused) cands.push_back({LBM_KERNEL_FUSED, r});
-        if (want_split) cands.push_back({LBM_KERNEL_SPLIT, r});
+        for (int nt = 0; nt < 2; ++nt) {
+            if ((nt && !want_nt) || (!nt && !want_cached)) continue;
+            if (want_fused) cands.push_back({LBM_KERNEL_FUSED, r, nt == 1});
+            if (want_split) cands.push_back({LBM_KERNEL_SPLIT, r, nt == 1});
+        }
     }
     if (cands.size() == 1) {
         c->kernel = cands[0].kernel;
         c->tile_rows = cands[0].rows;
+        c->nt_store = cands[0].nt;
         return LBM_OK;
     }
     HIPCHK(c, copy_n_async(c->q_tune, c->q, c->q_elems * sizeof(double), c->stream));
@@ -393,6 +405,7 @@ int autotune(lbm_ctx* c) {
     int rc = LBM_OK;
     for (const Cand& cd : cands) {
         StepArgs a = step_args(c, c->cur, true, cd.rows, cd.kernel == LBM_KERNEL_SPLIT, c->q_tune);
+        a.nt_store = cd.nt;
         StepArgs b = a;
         if (alt) {
             // temporary -> spare, then spare -> temporary
@@ -427,12 +440,14 @@ int autotune(lbm_ctx* c) {
         }
         if (rc != LBM_OK) break;
         std::sort(t, t + 3);
-        // candidates come smallest tile first; a later one must win by more than 2 %, so
-        // run-to-run noise does not flip the choice between near-equal configurations
+        // candidates come smallest tile first, cached stores before streaming ones; a
+        // later one must win by more than 2 %, so run-to-run noise does not flip the choice
+        // between near-equal configurations
         if (t[1] < 0.98f * best) {
             best = t[1];
             c->kernel = cd.kernel;
             c->tile_rows = cd.rows;
+            c->nt_store = cd.nt;
         }
     }
     hipEventDestroy(e0);
@@ -467,6 +482,7 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
     if (o.tile_rows != 0 && list_index(o.tile_rows) < 0)
         return fail(nullptr, LBM_ERR_PARAM, "tile_rows must be 0, 4, 8 or 16");
     if (o.check_every < 0) return fail(nullptr, LBM_ERR_PARAM, "check_every must be >= 0");
+    if (o.stores < 0 || o.stores > 2) return fail(nullptr, LBM_ERR_PARAM, "unknown store policy");
     const auto lattice_of = [](const lbm_params& q) {
         return q.f_lattice == 0 ? (int)LBM_LATTICE_D2Q9 : (int)q.f_lattice;
     };
@@ -618,7 +634,8 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
     c->step = 0;
     c->kernel = o.kernel == LBM_KERNEL_AUTO ? LBM_KERNEL_FUSED : o.kernel;
     c->tile_rows = o.tile_rows ? o.tile_rows : (c->storage == STORE_F64 ? 4 : 8);
-    if (o.kernel == LBM_KERNEL_AUTO || o.tile_rows == 0) {
+    c->nt_store = o.stores == LBM_STORES_STREAMING;
+    if (o.kernel == LBM_KERNEL_AUTO || o.tile_rows == 0 || o.stores == LBM_STORES_AUTO) {
         int rc = autotune(c);
         if (rc) return bail(rc);
     }
@@ -769,11 +786,13 @@ int lbm_set_state(lbm_ctx* c, const void* buf, size_t bytes) {
     return LBM_OK;
 }
 
-int lbm_info(const lbm_ctx* c, int64_t* step, int32_t* kernel, int32_t* tile_rows) {
+int lbm_info(const lbm_ctx* c, int64_t* step, int32_t* kernel, int32_t* tile_rows,
+             int32_t* stores) {
     if (!c) return fail(nullptr, LBM_ERR_PARAM, "context is NULL");
     if (step) *step = c->step;
     if (kernel) *kernel = c->kernel;
     if (tile_rows) *tile_rows = c->tile_rows;
+    if (stores) *stores = c->nt_store ? LBM_STORES_STREAMING : LBM_STORES_CACHED;
     return LBM_OK;
 }
 

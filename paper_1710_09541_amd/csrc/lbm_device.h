@@ -49,6 +49,7 @@ struct StepArgs {
     int qf;             // velocities of the phase-field lattice: 9 (D2Q9) or 5 (D2Q5)
     bool pull;          // false only for the first step (initial state in streamed form)
     bool split;         // two launches: phi plane, then stencil + collide
+    bool nt_store;      // non-temporal population stores
     const void* fsrc;
     const void* gsrc;
     void* fdst;

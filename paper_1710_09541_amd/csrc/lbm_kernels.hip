@@ -250,7 +250,19 @@ __device__ __forceinline__ int ghost_row(const InstDev& I, int y) {
     return y;
 }
 
-enum { MODE_STEP = 0, MODE_MOMENTS = 1 };
+// MODE_STEP_NT: a step whose population stores are non-temporal (they do not allocate in
+// the caches on their way to memory), which pays when the working set is larger than the
+// last-level cache and costs when it fits; the autotuner chooses.
+enum { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_STEP_NT = 2 };
+
+// store of a collided population, non-temporal in MODE_STEP_NT
+template <int MODE, typename S, typename C>
+__device__ __forceinline__ void put_pop(S* p, int o, C v) {
+    if constexpr (MODE == MODE_STEP_NT)
+        __builtin_nontemporal_store((S)v, (S*)((char*)p + (uint32_t)o * (uint32_t)sizeof(S)));
+    else
+        Store<S>::put(p, o, v);
+}
 
 // ------------------------------------------------------------------ FP64 node
 // The FP64 format keeps the operations and their order of the plain CPU reference
@@ -626,6 +638,9 @@ __device__ __forceinline__ void step_tile(
     const int plane = (int)I.plane;
     const C isf = SCALED ? C(I.inv_scale_f) : C(1), isg = SCALED ? C(I.inv_scale_g) : C(1);
 
+    // The loads of the tile are issued at raised wave priority (reduced formats), so a
+    // block's memory requests go out ahead of other waves' arithmetic.
+    if (REF) __builtin_amdgcn_s_setprio(3);
     // previous planes over the tile and a two-node halo (wrapped; clamped rows beyond a
     // wall or an open side are never sources)
     if (REF) {
@@ -709,7 +724,10 @@ __device__ __forceinline__ void step_tile(
             for (int i = 0; i < QF; ++i) rfv[i] = Store<S>::get(fb, o[i]);
         }
     }
-    if (REF) __syncthreads();
+    if (REF) {
+        __builtin_amdgcn_s_setprio(0);
+        __syncthreads();
+    }
 
     // phi of the tile's own nodes (and, reduced formats, its rounding residual)
     C res[K];
@@ -782,11 +800,11 @@ __device__ __forceinline__ void step_tile(
             const float qx = sw[me].x * sq[me].z, qy = sw[me].x * sq[me].w;
             node_update_ref<MODE, !PULL, QF>(I, fd, eg, gs, phi, r1[2], r2[1], r1[0], r0[1], r2[2], r2[0],
                                   r0[0], r0[2], res[k], qx, qy, fo, go, pw, mom);
-            if (MODE == MODE_STEP) {
+            if (MODE != MODE_MOMENTS) {
 #pragma unroll
-                for (int i = 0; i < QF; ++i) Store<S>::put(fo_b, i * plane + self, fo[i] * sf);
+                for (int i = 0; i < QF; ++i) put_pop<MODE>(fo_b, i * plane + self, fo[i] * sf);
 #pragma unroll
-                for (int i = 0; i < 9; ++i) Store<S>::put(go_b, i * plane + self, go[i] * sgs);
+                for (int i = 0; i < 9; ++i) put_pop<MODE>(go_b, i * plane + self, go[i] * sgs);
                 float* mo = mdst + I.off_mp;
                 st(mo, self, phi);
                 st(mo, plane + self, pw[0]);
@@ -799,11 +817,11 @@ __device__ __forceinline__ void step_tile(
             const double nb[9] = {phi, r1[2], r2[1], r1[0], r0[1], r2[2], r2[0], r0[0], r0[2]};
             double fo[9], go[9];
             node_update_f64<MODE, QF>(I, f[k], g[k], nb, qx, qy, fo, go, mom);
-            if (MODE == MODE_STEP) {
+            if (MODE != MODE_MOMENTS) {
 #pragma unroll
-                for (int i = 0; i < QF; ++i) Store<S>::put(fo_b, i * plane + self, fo[i]);
+                for (int i = 0; i < QF; ++i) put_pop<MODE>(fo_b, i * plane + self, fo[i]);
 #pragma unroll
-                for (int i = 0; i < 9; ++i) Store<S>::put(go_b, i * plane + self, go[i]);
+                for (int i = 0; i < 9; ++i) put_pop<MODE>(go_b, i * plane + self, go[i]);
                 qb[self] = qx;
                 qb[plane + self] = qy;
             }
@@ -990,7 +1008,14 @@ hipError_t step_k(const StepArgs& a) {
     } else if (a.split) {
         k_phi_plane<S, K, QF><<<grid, BLOCK, 0, a.stream>>>(a.insts, a.tiles, a.ntiles, per, fs,
                                                             rs, ph);
-        k_step<S, K, true, MODE_STEP, true, QF><<<grid, BLOCK, 0, a.stream>>>(
+        if (a.nt_store)
+            k_step<S, K, true, MODE_STEP_NT, true, QF><<<grid, BLOCK, 0, a.stream>>>(
+                a.insts, a.tiles, a.ntiles, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
+        else
+            k_step<S, K, true, MODE_STEP, true, QF><<<grid, BLOCK, 0, a.stream>>>(
+                a.insts, a.tiles, a.ntiles, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
+    } else if (a.nt_store) {
+        k_step<S, K, true, MODE_STEP_NT, false, QF><<<grid, BLOCK, 0, a.stream>>>(
             a.insts, a.tiles, a.ntiles, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
     } else {
         k_step<S, K, true, MODE_STEP, false, QF><<<grid, BLOCK, 0, a.stream>>>(

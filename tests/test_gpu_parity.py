@@ -299,3 +299,16 @@ def test_moments_device_matches_host():
         dev = buf.cpu().numpy().reshape(5, 24, 40)
     for i, k in enumerate(("phi", "rho", "p", "ux", "uy")):
         assert np.array_equal(dev[i], host[k])
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_streaming_stores_bitwise(storage):
+    """Non-temporal population stores (fused and split kernels) give the same bits as
+    ordinary ones."""
+    c = cases.droplet_impact(256, 96, D=40, Re=20)
+    ref = run_hip(c, 30, storage, kernel="fused", tile_rows=4, stores="cached")
+    for kw in (dict(kernel="fused", tile_rows=4, stores="streaming"),
+               dict(kernel="split", tile_rows=8, stores="streaming")):
+        got = run_hip(c, 30, storage, **kw)
+        for k in ref:
+            assert np.array_equal(ref[k], got[k]), kw
