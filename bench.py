@@ -91,13 +91,16 @@ def traffic_from_profile(wl, storage):
     return d.get("hbm_bytes_per_launch")
 
 
-def time_gpu(cs, storage, steps, warmup, kernel, tile_rows):
+def time_gpu(cs, storage, steps, warmup, kernel, tile_rows, final_stats=False):
+    """Milliseconds of `steps` steps after `warmup` untimed ones.  With final_stats, also
+    the first instance's L and sum(phi) drift at the end (read after the timed region)."""
     import torch
     from paper_1710_09541_amd import lbm
     stream = torch.cuda.Stream()
     sim = lbm.Simulation(cs, storage=storage, kernel=kernel, tile_rows=tile_rows,
                          stream=stream.cuda_stream)
     info = sim.info()
+    s0 = sim.reduce()["sum_phi"] if final_stats else None
     sim.step(warmup)
     stream.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -107,21 +110,27 @@ def time_gpu(cs, storage, steps, warmup, kernel, tile_rows):
     e1.record(stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1)
+    stats = None
+    if final_stats:
+        phi = sim.moments(0)["phi"]
+        stats = {"steps": warmup + steps, "L": crossings_length(phi),
+                 "sum_phi_drift": abs(float(sim.reduce()["sum_phi"]) - s0) / s0}
     sim.close()
-    return ms, info
+    return ms, info, stats
 
 
-def measure(cs, storage, steps, warmup, kernel="auto", tile_rows=0):
+def measure(cs, storage, steps, warmup, kernel="auto", tile_rows=0, final_stats=False):
     nodes = sum(c["nx"] * c["ny"] for c in cs)
     qf = cs[0].get("f_lattice", 9)
-    ms, info = time_gpu(cs, storage, steps, warmup, kernel, tile_rows)
+    ms, info, stats = time_gpu(cs, storage, steps, warmup, kernel, tile_rows, final_stats)
     per_launch_s = ms / 1e3 / steps
     ach = alg_bytes(storage, qf) * nodes / per_launch_s / 1e9
     return {"mlups": nodes * steps / (ms / 1e3) / 1e6, "ms_per_step": ms / steps,
             "kernel": info["kernel"], "tile_rows": info["tile_rows"], "stores": info["stores"],
             "f_lattice": qf,
             "alg_bytes_per_lu": alg_bytes(storage, qf), "achieved_gbs": ach,
-            "frac_hbm_peak": ach / PEAK_HBM_GBS, "nodes": nodes, "steps": steps}
+            "frac_hbm_peak": ach / PEAK_HBM_GBS, "nodes": nodes, "steps": steps,
+            **({"end_of_run": stats} if stats else {})}
 
 
 def crossings_length(phi):
@@ -240,7 +249,8 @@ def main():
     pois_ref = {}
     others = [] if args.variants in ("", "none") else args.variants.split(",")
     for st in [args.storage] + [v for v in others if v and v != args.storage]:
-        r = measure(cs, st, args.steps, args.warmup, args.kernel, args.tile_rows)
+        r = measure(cs, st, args.steps, args.warmup, args.kernel, args.tile_rows,
+                    final_stats=single)
         log("%s: %.1f MLUPS, %.4f ms/step, %.0f GB/s algorithmic" % (st, r["mlups"],
                                                                       r["ms_per_step"],
                                                                       r["achieved_gbs"]))
@@ -251,6 +261,17 @@ def main():
             r["parity_vs_oracle"] = poiseuille_parity(st, pois_ref)
             log("%s: parity %s" % (st, json.dumps(r["parity_vs_oracle"])))
         results[st] = r
+
+    # end of the timed runs: L of each format against the FP64 format's (which repeats the
+    # oracle's arithmetic), over the whole timed horizon
+    if "f64" in results and "end_of_run" in results["f64"]:
+        L64 = results["f64"]["end_of_run"]["L"]
+        for st, r in results.items():
+            if "end_of_run" in r:
+                r["end_of_run"]["L_rel_to_f64"] = abs(r["end_of_run"]["L"] / L64 - 1)
+                log("%s: after %d steps L %.4f (rel. to FP64 %.2e), sum phi drift %.2e"
+                    % (st, r["end_of_run"]["steps"], r["end_of_run"]["L"],
+                       r["end_of_run"]["L_rel_to_f64"], r["end_of_run"]["sum_phi_drift"]))
 
     extra = {}
     if not args.no_extra and args.workload == "spinodal1024":

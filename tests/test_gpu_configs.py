@@ -94,3 +94,59 @@ def test_batch_16_instances_1000_steps():
         if e["phi"] > bound:
             bound = max(bound, 4.0 * sensitivity(c, 1000)["phi"])
         assert e["phi"] <= bound
+
+
+def _length(phi):
+    s = phi >= 0.5
+    cr = np.count_nonzero(s != np.roll(s, 1, axis=1)) + np.count_nonzero(s != np.roll(s, 1, axis=0))
+    return 2.0 * phi.size / cr
+
+
+def test_spinodal_1024_20000_steps_reduced_vs_fp64():
+    """The spinodal run as specified (1024^2, 20,000 steps): the coarsening length L(t) of
+    FP32 and FP16 storage against the FP64 format (which repeats the oracle's arithmetic
+    bit for bit) every 4000 steps, and the drift of sum(phi)."""
+    c = cases.spinodal(1024, seed=0)
+    sims = {st: lbm.Simulation(c, storage=st) for st in ("f64", "f32", "f16")}
+    s0 = {st: sims[st].reduce()["sum_phi"] for st in sims}
+    try:
+        for t in range(4000, 20001, 4000):
+            L = {}
+            for st, sim in sims.items():
+                sim.step(4000)
+                L[st] = _length(sim.moments()["phi"])
+            print("[spinodal1024] step %d: L f64 %.3f f32 %.3f f16 %.3f" % (t, L["f64"], L["f32"],
+                                                                          L["f16"]), flush=True)
+            assert abs(L["f32"] / L["f64"] - 1) < 0.05
+            assert abs(L["f16"] / L["f64"] - 1) < 0.05
+        drift = {st: abs(sims[st].reduce()["sum_phi"] - s0[st]) / s0[st] for st in sims}
+        print("[spinodal1024] sum phi drift after 20000 steps: %s" % drift, flush=True)
+        # FP64: round-off only, the bound of the oracle's conservation pin (20 eps per step)
+        assert drift["f64"] < 20 * np.finfo(float).eps * 20000
+        assert drift["f32"] < 1e-6 and drift["f16"] < 1e-4
+    finally:
+        for sim in sims.values():
+            sim.close()
+
+
+def test_impact_full_size_spreading_reduced_vs_fp64():
+    """The impact at full size (2048 x 512, D = 256, Re = 100): the spreading radius of FP32
+    and FP16 storage against the FP64 format at t* = 0.5, 1 and 2."""
+    c = cases.droplet_impact(2048, 512, D=256, Re=100)
+    T = c["D"] / c["U"]
+    sims = {st: lbm.Simulation(c, storage=st) for st in ("f64", "f32", "f16")}
+    try:
+        for t in (0.5, 1.0, 2.0):
+            r = {}
+            for st, sim in sims.items():
+                sim.step(int(round(t * T)) - sim.info()["step"])
+                d = sim.reduce()
+                assert d["nonfinite"] == 0
+                r[st] = d["spread_radius"] / c["D"]
+            print("[spreading 2048x512] t*=%.1f: r/D f64 %.4f f32 %.4f f16 %.4f"
+                  % (t, r["f64"], r["f32"], r["f16"]), flush=True)
+            assert abs(r["f32"] / r["f64"] - 1) < 0.01
+            assert abs(r["f16"] / r["f64"] - 1) < 0.02
+    finally:
+        for sim in sims.values():
+            sim.close()
