@@ -1,10 +1,12 @@
 /*
  * lbm.h -- C-ABI of the MI355X (gfx950) phase-field lattice Boltzmann library.
  *
- * The library advances the two coupled D2Q9 lattices of Liang et al., "Phase-field-based
- * lattice Boltzmann modeling of large-density-ratio two-phase flows" (arXiv:1710.09541):
- *   f_i  conservative Allen-Cahn equation for the order parameter phi  (Sec. 2.2, Eqs. 8-14)
- *   g_i  incompressible Navier-Stokes with the forcing distribution G_i (Sec. 2.3, Eqs. 15-28)
+ * The library advances the two coupled lattices of Liang et al., "Phase-field-based lattice
+ * Boltzmann modeling of large-density-ratio two-phase flows" (arXiv:1710.09541):
+ *   f_i  conservative Allen-Cahn equation for the order parameter phi  (Sec. 2.2, Eqs. 8-14;
+ *        D2Q9, or D2Q5, which the section also admits)
+ *   g_i  incompressible Navier-Stokes with the forcing distribution G_i (Sec. 2.3, Eqs. 15-28;
+ *        D2Q9)
  * on one GPU, for one or many independent instances ("batch") at once.
  *
  * Problem statement (Sec. 2.1 and the set-ups of Sec. 3): a 2D nx x ny lattice with

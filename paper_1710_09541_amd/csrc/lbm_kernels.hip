@@ -30,6 +30,13 @@
 //   open       zero gradient: an incoming population of the edge row equals the streamed
 //              value of the row inside it, i.e. f*_i(x - c_ix, edge row)
 // The stencil's ghost rows at walls and open sides mirror the edge row.
+//
+// Variants, all compile-time: storage format S; rows per thread K (tiles of 64 x 4K nodes);
+// PULL (false only for the first step); MODE (step, step with non-temporal population
+// stores, or moments only); RING_FROM_PLANE (split step); INTERIOR (tiles away from every
+// edge); QF, the velocities of the phase-field lattice (9 or 5).  The normal in F_i comes
+// from the isotropic stencil (Eq. 2 with Eq. 27) or, per instance, from the local
+// non-equilibrium scheme of Eq. 29, n = -C/|C|.
 #include "lbm_device.h"
 
 #include <math.h>

@@ -366,7 +366,7 @@ def test_galilean_translation():
     recovered equation Galilean invariant)."""
     c = cases.planar_interface(nx=4, ny=64, W=4.0, ratio=1.0, sigma=0.0, uy=0.02)
     s = O.OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
-    s.step(3200)     # 64 / 0.02 steps: once round the box
+    s.step(3200)     # 64 / 0.02 steps: once around the periodic domain
     phi = s.moments()["phi"]
     assert np.max(np.abs(phi - c["phi0"])) < 0.02
 
