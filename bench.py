@@ -53,9 +53,19 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def code_hash(text):
+    """sha256 (first 16 hex digits) of C++ source with comments and blank space removed, so
+    that only a change of the code itself marks measurements taken on it as stale."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    text = "\n".join(" ".join(l.split()) for l in text.splitlines() if l.strip())
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
 def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    with open(KERNEL_SRC) as fh:
+        return code_hash(fh.read())
 
 
 def workload(name):
