@@ -40,22 +40,29 @@ __device__ __forceinline__ void red_join(double (&a)[NRED], const double* b) {
     a[R_NONFIN] += b[R_NONFIN];
 }
 
-// fixed-shape tree over the block's 256 slots in LDS
+// Wavefront reduction: a fixed-shape tree over the 64 lanes with cross-lane shuffles
+// (lane l takes lane l + s for s = 32, 16, ..., 1), then lane 0 of each of the block's 4
+// wavefronts leaves its result in LDS and thread 0 folds the 4 in wavefront order.  The
+// shape never depends on timing, so the result is deterministic.  Thread 0 ends with the
+// block's result.
+constexpr int WAVE = 64;
 __device__ __forceinline__ void block_fold(double (&acc)[NRED], double* sh) {
     const int tid = threadIdx.x;
 #pragma unroll
-    for (int k = 0; k < NRED; ++k) sh[k * BLOCK + tid] = acc[k];
+    for (int s = WAVE / 2; s > 0; s >>= 1) {
+        double other[NRED];
+#pragma unroll
+        for (int k = 0; k < NRED; ++k) other[k] = __shfl_down(acc[k], s, WAVE);
+        red_join(acc, other);   // lanes >= 64 - s fold in values they do not use
+    }
+    const int wave = tid / WAVE;
+    if ((tid & (WAVE - 1)) == 0) {
+#pragma unroll
+        for (int k = 0; k < NRED; ++k) sh[wave * NRED + k] = acc[k];
+    }
     __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-        if (tid < s) {
-            double other[NRED];
-#pragma unroll
-            for (int k = 0; k < NRED; ++k) other[k] = sh[k * BLOCK + tid + s];
-            red_join(acc, other);
-#pragma unroll
-            for (int k = 0; k < NRED; ++k) sh[k * BLOCK + tid] = acc[k];
-        }
-        __syncthreads();
+    if (tid == 0) {
+        for (int wv = 1; wv < BLOCK / WAVE; ++wv) red_join(acc, sh + wv * NRED);
     }
 }
 
@@ -63,7 +70,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_partial(const double* __restri
                                                           int ny, int periodic_y, double xc,
                                                           double yc, double r_in, double r_out,
                                                           double* __restrict__ partials) {
-    __shared__ double sh[NRED * BLOCK];
+    __shared__ double sh[NRED * (BLOCK / WAVE)];
     double acc[NRED];
     red_init(acc);
     const int64_t n = (int64_t)nx * ny;
@@ -125,7 +132,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_final(const double* __restrict
                                                         const double* __restrict__ mom, int nx,
                                                         int ny, double xc, int y_row,
                                                         double* __restrict__ out) {
-    __shared__ double sh[NRED * BLOCK];
+    __shared__ double sh[NRED * (BLOCK / WAVE)];
     double acc[NRED];
     red_init(acc);
     for (int b = threadIdx.x; b < nblocks; b += BLOCK) red_join(acc, partials + (int64_t)b * NRED);
