@@ -15,8 +15,10 @@ same device and reported next to it, each with its error against the FP64 CPU or
   step viscosity, density ratio 1000), where the stated tolerances apply.
 
 Also timed: the same spinodal at 4096 x 4096 (working set far above the 256 MB last-level
-cache, so the bandwidth is HBM's), a batch of 256 independent instances of uneven size, and
-the spinodal with the D2Q5 phase-field lattice (5 instead of 9 f populations).
+cache, so the bandwidth is HBM's), a batch of 256 independent instances of uneven size, the
+spinodal with the D2Q5 phase-field lattice (5 instead of 9 f populations), the static drop
+64 x 64 and the Poiseuille channel 16 x 512 (both so small that launch latency dominates),
+and the droplet impact at 2048 x 512.
 
 Prints ONE JSON line.  Inputs are resident in device memory before the timed region;
 timing uses HIP events recorded on the stream the library launches on.
@@ -298,6 +300,15 @@ def main():
             extra["spinodal1024_d2q5_" + st] = r
             log("1024^2 D2Q5 %s: %.1f MLUPS, %.0f GB/s algorithmic" % (st, r["mlups"],
                                                                        r["achieved_gbs"]))
+        from paper_1710_09541_amd import cases
+        small = [("static_drop64_f64", [cases.static_drop()], "f64", 2000),
+                 ("poiseuille16x512_f32", [cases.layered_poiseuille()], "f32", 5000),
+                 ("impact2048_f32", workload("impact2048")[0], "f32", 2000),
+                 ("impact2048_f16", workload("impact2048")[0], "f16", 2000)]
+        for name, wcs, st, n in small:
+            r = measure(wcs, st, n, 50)
+            extra[name] = r
+            log("%s: %.1f MLUPS, %.4f ms/step" % (name, r["mlups"], r["ms_per_step"]))
         bcs, bdesc = workload("batch256")
         for st in ("f32", "f64"):
             r = measure(bcs, st, 200, 10)
