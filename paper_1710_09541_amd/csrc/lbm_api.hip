@@ -75,7 +75,9 @@ struct lbm_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};  // two steps starting from buffer 0 / 1
+    // captured step sequences starting from buffer 0 / 1: graph[g][from] holds
+    // GRAPH_STEPS[g] consecutive steps (an even number, so the buffer parity returns)
+    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     int cur = 0;               // buffer holding the current state
     bool streamed = true;      // the current state is still the initial, streamed one
     int64_t step = 0;
@@ -217,8 +219,10 @@ std::vector<TileDesc> build_tiles(const std::vector<Instance>& v, int rows) {
 
 void free_all(lbm_ctx* c) {
     for (int i = 0; i < 2; ++i) {
-        if (c->graph[i]) hipGraphExecDestroy(c->graph[i]);
-        c->graph[i] = nullptr;
+        for (int g = 0; g < 2; ++g) {
+            if (c->graph[g][i]) hipGraphExecDestroy(c->graph[g][i]);
+            c->graph[g][i] = nullptr;
+        }
         if (c->f[i]) hipFree(c->f[i]);
         if (c->g[i]) hipFree(c->g[i]);
         c->f[i] = c->g[i] = nullptr;
@@ -275,22 +279,27 @@ int launch_one(lbm_ctx* c, hipStream_t st) {
 }
 
 void drop_graphs(lbm_ctx* c) {
-    for (int i = 0; i < 2; ++i) {
-        if (c->graph[i]) hipGraphExecDestroy(c->graph[i]);
-        c->graph[i] = nullptr;
-    }
+    for (int g = 0; g < 2; ++g)
+        for (int i = 0; i < 2; ++i) {
+            if (c->graph[g][i]) hipGraphExecDestroy(c->graph[g][i]);
+            c->graph[g][i] = nullptr;
+        }
 }
 
-// captures two consecutive steps starting from buffer `from`
-int capture_pair(lbm_ctx* c, int from) {
+// steps per captured graph: a short one and a long one (fewer launches per step, which is
+// what bounds small grids)
+constexpr int GRAPH_STEPS[2] = {2, 16};
+
+// captures GRAPH_STEPS[g] consecutive steps starting from buffer `from`
+int capture_steps(lbm_ctx* c, int g, int from) {
     if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     const int save_cur = c->cur;
     const bool save_streamed = c->streamed;
     c->cur = from;
     c->streamed = false;
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = launch_one(c, c->cap_stream);
-    if (rc == LBM_OK) rc = launch_one(c, c->cap_stream);
+    int rc = LBM_OK;
+    for (int k = 0; k < GRAPH_STEPS[g] && rc == LBM_OK; ++k) rc = launch_one(c, c->cap_stream);
     hipGraph_t gr = nullptr;
     hipError_t e = hipStreamEndCapture(c->cap_stream, &gr);
     c->cur = save_cur;
@@ -300,7 +309,7 @@ int capture_pair(lbm_ctx* c, int from) {
         return rc;
     }
     if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
-    e = hipGraphInstantiate(&c->graph[from], gr, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&c->graph[g][from], gr, nullptr, nullptr, 0);
     hipGraphDestroy(gr);
     if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
     return LBM_OK;
@@ -657,15 +666,16 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
         }
         int64_t done = 0;
         while (done < chunk) {
-            if (!c->streamed && c->opt.use_graph && chunk - done >= 2) {
-                if (!c->graph[c->cur]) {
-                    int rc = capture_pair(c, c->cur);
+            if (!c->streamed && c->opt.use_graph && chunk - done >= GRAPH_STEPS[0]) {
+                const int g = chunk - done >= GRAPH_STEPS[1] ? 1 : 0;
+                if (!c->graph[g][c->cur]) {
+                    int rc = capture_steps(c, g, c->cur);
                     if (rc) return rc;
                 }
-                hipError_t e = hipGraphLaunch(c->graph[c->cur], c->stream);
+                hipError_t e = hipGraphLaunch(c->graph[g][c->cur], c->stream);
                 if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
-                done += 2;
-                c->step += 2;
+                done += GRAPH_STEPS[g];
+                c->step += GRAPH_STEPS[g];
             } else {
                 int rc = launch_one(c, c->stream);
                 if (rc) return rc;
