@@ -363,7 +363,7 @@ int check_finite(lbm_ctx* c) {
 // is left untouched.  (The alternation matters: the buffer a step reads was written by the
 // step before, partly still in the last-level cache.)  If the temporary cannot be
 // allocated, the launches repeat from the current buffer into the spare one.  The fastest
-// median wins, by a margin of 2 % over smaller tiles.
+// median of interleaved rounds wins, by a margin of 2 % over smaller tiles.
 int autotune(lbm_ctx* c) {
     struct Cand {
         int kernel, rows;
@@ -398,24 +398,43 @@ int autotune(lbm_ctx* c) {
     bool alt = hipMalloc(&tf, dbytes) == hipSuccess && hipMalloc(&tg, dbytes) == hipSuccess &&
                (rbytes == 0 || hipMalloc(&tr, rbytes) == hipSuccess);
     (void)hipGetLastError();
-    if (alt) {
-        HIPCHK(c, hipMemcpyAsync(tf, c->f[c->cur], dbytes, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(tg, c->g[c->cur], dbytes, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, copy_n_async(tr, c->rplane[c->cur], rbytes, c->stream));
+    auto free_temps = [&]() {
+        if (tf) (void)hipFree(tf);
+        if (tg) (void)hipFree(tg);
+        if (tr) (void)hipFree(tr);
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    {
+        hipError_t e = hipSuccess;
+        if (alt) {
+            e = hipMemcpyAsync(tf, c->f[c->cur], dbytes, hipMemcpyDeviceToDevice, c->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(tg, c->g[c->cur], dbytes, hipMemcpyDeviceToDevice, c->stream);
+            if (e == hipSuccess) e = copy_n_async(tr, c->rplane[c->cur], rbytes, c->stream);
+        }
+        if (e == hipSuccess) e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e != hipSuccess) {
+            if (e0) hipEventDestroy(e0);
+            free_temps();
+            return hip_fail(c, e, "autotune set-up");
+        }
     }
-    hipEvent_t e0, e1;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
     int64_t nodes = 0;
     for (auto& I : c->inst) nodes += I.n_nodes;
     // an even number of launches: whole temporary -> spare -> temporary pairs
     const int reps = 2 * std::max(2, (int)std::min<int64_t>(25, 100000000 / std::max<int64_t>(nodes, 1)));
-    float best = 1e30f;
+    // Every candidate runs once untimed (clocks and caches reach their running state), then
+    // NREP timed rounds visit the candidates in turn, so a slow drift of the clocks does not
+    // favour the candidates timed first; the median of each candidate's rounds decides.
+    constexpr int NREP = 5;
+    const int nc = (int)cands.size();
+    std::vector<float> t((size_t)nc * NREP, 0.0f);
     int rc = LBM_OK;
-    for (const Cand& cd : cands) {
-        StepArgs a = step_args(c, c->cur, true, cd.rows, cd.kernel == LBM_KERNEL_SPLIT, c->q_tune);
+    auto args_of = [&](const Cand& cd, StepArgs& a, StepArgs& b) {
+        a = step_args(c, c->cur, true, cd.rows, cd.kernel == LBM_KERNEL_SPLIT, c->q_tune);
         a.nt_store = cd.nt;
-        StepArgs b = a;
+        b = a;
         if (alt) {
             // temporary -> spare, then spare -> temporary
             a.fsrc = tf;
@@ -428,8 +447,11 @@ int autotune(lbm_ctx* c) {
             b.gdst = tg;
             b.rdst = tr;
         }
-        float t[3];
-        for (int r = 0; r < 3 && rc == LBM_OK; ++r) {
+    };
+    for (int round = -1; round < NREP && rc == LBM_OK; ++round) {
+        for (int ci = 0; ci < nc && rc == LBM_OK; ++ci) {
+            StepArgs a, b;
+            args_of(cands[ci], a, b);
             hipEventRecord(e0, c->stream);
             for (int k = 0; k < reps; ++k) {
                 hipError_t e = launch_step(c->storage, (k & 1) ? b : a);
@@ -445,25 +467,28 @@ int autotune(lbm_ctx* c) {
                 rc = hip_fail(c, e, "autotune synchronize");
                 break;
             }
-            hipEventElapsedTime(&t[r], e0, e1);
+            if (round >= 0) hipEventElapsedTime(&t[(size_t)ci * NREP + round], e0, e1);
         }
-        if (rc != LBM_OK) break;
-        std::sort(t, t + 3);
-        // candidates come smallest tile first, cached stores before streaming ones; a
-        // later one must win by more than 2 %, so run-to-run noise does not flip the choice
-        // between near-equal configurations
-        if (t[1] < 0.98f * best) {
-            best = t[1];
-            c->kernel = cd.kernel;
-            c->tile_rows = cd.rows;
-            c->nt_store = cd.nt;
+    }
+    if (rc == LBM_OK) {
+        // candidates come smallest tile first, cached stores before streaming ones; a later
+        // one must win by more than 2 %, so run-to-run noise does not flip the choice between
+        // near-equal configurations
+        float best = 1e30f;
+        for (int ci = 0; ci < nc; ++ci) {
+            float* tc = t.data() + (size_t)ci * NREP;
+            std::sort(tc, tc + NREP);
+            if (tc[NREP / 2] < 0.98f * best) {
+                best = tc[NREP / 2];
+                c->kernel = cands[ci].kernel;
+                c->tile_rows = cands[ci].rows;
+                c->nt_store = cands[ci].nt;
+            }
         }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    if (tf) (void)hipFree(tf);
-    if (tg) (void)hipFree(tg);
-    if (tr) (void)hipFree(tr);
+    free_temps();
     return rc;
 }
 
