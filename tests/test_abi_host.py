@@ -117,3 +117,15 @@ def test_mixed_phase_field_lattices_rejected():
                      [a["phi0"], b["phi0"]], [a["ux0"], b["ux0"]], [a["uy0"], b["uy0"]])
     assert e.value.code == lbm.LBM_ERR_PARAM
     assert "lattice" in lbm.lbm_last_error()
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built HIP library the binding raises; nothing falls back to another
+    implementation."""
+    monkeypatch.setattr(lbm, "_lib", None)
+    monkeypatch.setattr(lbm, "LIB_PATH", "/nonexistent/liblbm_hip.so")
+    with pytest.raises(RuntimeError, match="not built"):
+        lbm.load()
+    c = cases.static_drop(8, 8, R=2)
+    with pytest.raises(RuntimeError):
+        lbm.Simulation(c, storage="f64")
