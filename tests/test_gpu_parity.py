@@ -312,3 +312,11 @@ def test_streaming_stores_bitwise(storage):
         got = run_hip(c, 30, storage, **kw)
         for k in ref:
             assert np.array_equal(ref[k], got[k]), kw
+
+
+@pytest.mark.parametrize("storage,fields", [("f32", ("phi", "u")), ("f16", ("u",))])
+def test_inverse_viscosity_law_reduced_storage(storage, fields):
+    """Eq. 25 on the layered channel (walls, ratio 1000, nu_g / nu_l = 10) in the reduced
+    formats against the oracle after 1000 steps."""
+    c = cases.layered_poiseuille(visc_law=cases.NU_INVERSE)
+    _check("poiseuille inverse nu", c, 1000, storage, fields)

@@ -375,7 +375,7 @@ def test_galilean_translation():
 
 @pytest.mark.parametrize("bc", [(cases.PERIODIC, cases.PERIODIC), (cases.WALL, cases.WALL),
                                 (cases.WALL, cases.OPEN), (cases.OPEN, cases.WALL)])
-@pytest.mark.parametrize("law", [cases.NU_LINEAR, cases.MU_STEP])
+@pytest.mark.parametrize("law", [cases.NU_LINEAR, cases.NU_INVERSE, cases.MU_STEP])
 @pytest.mark.parametrize("scheme", [cases.GRAD_ISOTROPIC, cases.GRAD_LOCAL_NEQ])
 @pytest.mark.parametrize("qf", [9, 5])
 def test_bruteforce_4x4(bc, law, scheme, qf):
@@ -648,3 +648,36 @@ def test_d2q5_galilean_translation():
         s.step(int(64 / 0.05))
         res[qf] = float(np.max(np.abs(s.moments()["phi"] - c["phi0"])))
     assert res[5] < 0.05 and res[9] < 0.05
+
+
+# ------------------------------------- inverse-linear viscosity and mobility (NEXT f3)
+
+@pytest.mark.parametrize("M", [0.02, 0.1, 0.5])
+def test_inverse_viscosity_mobility_sweep_static_drop(M):
+    """Eq. 25 (1/nu linear in phi) on the static drop of Sec. 3.1 at ratio 1000 with
+    nu_l != nu_g, over a range of mobilities (tau_phi = 3M + 0.5): the drop stays at rest,
+    the centre-line density follows rho(phi_tanh) (Eq. 13 on Eq. 30) and the pressure jump
+    obeys the Young-Laplace law within 10 % at W = 4 (measured 1.06 sigma/R for each M)."""
+    c = cases.static_drop(64, 64, R=16.0, W=4.0, sigma=0.01, M=M, visc_law=cases.NU_INVERSE)
+    c["nu_g"] = 0.3
+    s = O.OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
+    s.step(3000)
+    m = s.moments()
+    assert np.sqrt(m["ux"] ** 2 + m["uy"] ** 2).max() < 5e-2 * c["sigma"] / (c["rho_l"] * 0.1)
+    rho0 = c["phi0"] * (c["rho_l"] - c["rho_g"]) + c["rho_g"]
+    assert np.max(np.abs(m["rho"][32] - rho0[32])) < 2e-2 * c["rho_l"]
+    d = diag.diagnostics(m, c["rho_l"], c["rho_g"], c["mask"])
+    assert 0.9 < (d["p_in"] - d["p_out"]) * 16.0 / 0.01 < 1.1
+
+
+def test_inverse_viscosity_law_values():
+    """Eq. 25 through the closure: nu equals nu_l at phi = 1, nu_g at phi = 0, and the
+    harmonic interpolation 1/nu = phi/nu_l + (1 - phi)/nu_g in between (tau_g = 3 nu + 1/2,
+    Eq. 23)."""
+    c = cases.static_drop(8, 8, R=2, visc_law=cases.NU_INVERSE)
+    c["nu_l"], c["nu_g"] = 0.1, 0.4
+    g = np.zeros(9)
+    for phi in (0.0, 0.25, 0.5, 1.0):
+        out = O.closure(c, phi, 0.0, 0.0, 0.0, g)
+        nu = 1.0 / (phi / 0.1 + (1.0 - phi) / 0.4)
+        assert abs(out["tau_g"] - (3.0 * nu + 0.5)) < 1e-14
