@@ -118,7 +118,11 @@ typedef struct {
     int32_t use_graph;        /* 1: lbm_step replays captured HIP graphs of two steps */
     int32_t check_every;      /* > 0: every that many steps lbm_step checks for non-finite
                                  values and returns LBM_ERR_NONFINITE (synchronises) */
-    int32_t stores;           /* LBM_STORES_* */
+    int32_t stores;           /* LBM_STORES_* (with kernel / tile_rows AUTO or 0 the choice is
+                                 timed at lbm_init; if the environment variable
+                                 LBM_AUTOTUNE_CACHE names a file, choices are read from and
+                                 appended to it, keyed by GPU, storage, lattice, options and
+                                 grid sizes) */
     int32_t reserved[2];
 } lbm_options;
 

@@ -9,6 +9,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -356,6 +358,60 @@ int check_finite(lbm_ctx* c) {
     return LBM_OK;
 }
 
+// ------------------------------------------------------------------ autotuner cache
+// If the environment variable LBM_AUTOTUNE_CACHE names a file, tuned choices are kept there,
+// one text line per configuration:
+//   lbm-tune-v1 <key> <kernel> <tile_rows> <streaming stores 0/1>
+// The key covers everything the timing depends on: the GPU architecture, storage, phase-
+// field lattice, the requested kernel / tile rows / store policy, the number of instances
+// and every instance's grid size.  A missing, unreadable or malformed file only means the
+// tuner runs; a write failure is ignored.
+std::string tune_key(const lbm_ctx* c) {
+    std::ostringstream k;
+    hipDeviceProp_t prop;
+    int dev = 0;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        arch = prop.gcnArchName;
+    for (char& ch : arch)
+        if (ch == ' ') ch = '_';
+    k << arch << ":s" << c->storage << ":q" << c->qf << ":k" << c->opt.kernel << ":r"
+      << c->opt.tile_rows << ":w" << c->opt.stores << ":n" << c->inst.size();
+    for (const Instance& I : c->inst) k << ":" << I.p.nx << "x" << I.p.ny;
+    return k.str();
+}
+
+bool tune_cache_lookup(lbm_ctx* c, const std::string& key) {
+    const char* path = getenv("LBM_AUTOTUNE_CACHE");
+    if (!path || !*path) return false;
+    std::ifstream in(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(in, line)) {
+        std::istringstream ls(line);
+        std::string tag, k;
+        int kernel = 0, rows = 0, nt = 0;
+        if (!(ls >> tag >> k >> kernel >> rows >> nt) || tag != "lbm-tune-v1" || k != key)
+            continue;
+        if ((kernel != LBM_KERNEL_FUSED && kernel != LBM_KERNEL_SPLIT) || list_index(rows) < 0 ||
+            (nt != 0 && nt != 1))
+            continue;
+        c->kernel = kernel;   // the last valid line for the key wins
+        c->tile_rows = rows;
+        c->nt_store = nt == 1;
+        found = true;
+    }
+    return found;
+}
+
+void tune_cache_store(const lbm_ctx* c, const std::string& key) {
+    const char* path = getenv("LBM_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    std::ofstream out(path, std::ios::app);
+    if (out) out << "lbm-tune-v1 " << key << " " << c->kernel << " " << c->tile_rows << " "
+                 << (c->nt_store ? 1 : 0) << "\n";
+}
+
 // ------------------------------------------------------------------ autotuner
 // Times each candidate (kernel, tile rows) on the context's own data, launched the way the
 // time loop launches them: alternating between two buffers, here the spare buffer and a
@@ -670,8 +726,12 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
     c->tile_rows = o.tile_rows ? o.tile_rows : (c->storage == STORE_F64 ? 4 : 8);
     c->nt_store = o.stores == LBM_STORES_STREAMING;
     if (o.kernel == LBM_KERNEL_AUTO || o.tile_rows == 0 || o.stores == LBM_STORES_AUTO) {
-        int rc = autotune(c);
-        if (rc) return bail(rc);
+        const std::string key = tune_key(c);
+        if (!tune_cache_lookup(c, key)) {
+            int rc = autotune(c);
+            if (rc) return bail(rc);
+            tune_cache_store(c, key);
+        }
     }
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return bail(hip_fail(c, e, "init synchronise"));

@@ -320,3 +320,32 @@ def test_inverse_viscosity_law_reduced_storage(storage, fields):
     formats against the oracle after 1000 steps."""
     c = cases.layered_poiseuille(visc_law=cases.NU_INVERSE)
     _check("poiseuille inverse nu", c, 1000, storage, fields)
+
+
+def test_autotune_cache(tmp_path, monkeypatch):
+    """LBM_AUTOTUNE_CACHE: the first context tunes and records its choice; a second context
+    with the same key takes it from the file; malformed lines are ignored; results are the
+    same bits either way."""
+    path = tmp_path / "tune.txt"
+    path.write_text("garbage line\nlbm-tune-v1 only-three-fields 1\n")
+    monkeypatch.setenv("LBM_AUTOTUNE_CACHE", str(path))
+    c = cases.droplet_impact(256, 96, D=40, Re=20)
+    with lbm.Simulation(c, storage="f32") as a:
+        info_a = a.info()
+        a.step(20)
+        ref = a.moments()
+    lines = [l for l in path.read_text().splitlines() if l.startswith("lbm-tune-v1 ") and
+             len(l.split()) == 5]
+    assert len(lines) == 1
+    kern, rows, nt = (int(v) for v in lines[0].split()[2:])
+    assert (kern, rows) == (info_a["kernel"], info_a["tile_rows"])
+    with lbm.Simulation(c, storage="f32") as b:
+        info_b = b.info()
+        b.step(20)
+        got = b.moments()
+    assert [l for l in path.read_text().splitlines() if l.startswith("lbm-tune-v1 ") and
+            len(l.split()) == 5] == lines          # found in the cache: nothing appended
+    assert (info_b["kernel"], info_b["tile_rows"], info_b["stores"]) == \
+        (info_a["kernel"], info_a["tile_rows"], info_a["stores"])
+    for k in ref:
+        assert np.array_equal(ref[k], got[k])
