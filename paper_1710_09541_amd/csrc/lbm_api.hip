@@ -60,13 +60,13 @@ struct lbm_ctx {
     int64_t dist_elems = 0;    // elements of one distribution set (all instances, 9 planes)
     int64_t q_elems = 0;       // FP64 phi u: 2 double planes per instance
     int64_t phi_elems = 0;     // split-kernel phi: 1 plane per instance
-    int64_t mp_elems = 0;      // reduced formats: 4 float planes per instance
+    int64_t mp_elems = 0;      // reduced formats: a float4 per node and instance
     void* f[2] = {nullptr, nullptr};
     void* g[2] = {nullptr, nullptr};
     void* q = nullptr;
     void* q_tune = nullptr;
     void* phiplane = nullptr;
-    void* rplane[2] = {nullptr, nullptr};  // planes phi_w, p_w, u_w written with buffer i
+    void* rplane[2] = {nullptr, nullptr};  // (phi_w, p_w, u_w) per node, written with buffer i
     InstDev* d_insts = nullptr;
     TileList lists[3];         // 4, 8, 16 rows
     double* mom = nullptr;     // 5 * max nodes, moments scratch
@@ -604,7 +604,7 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
         I.d.off_mp = off_mp;
         off_dist += round_up(9 * I.d.plane, 64);
         // phi u of the previous step: two double planes (FP64 format) or, in the reduced
-        // formats, the four FP32 planes phi_w, p_w, u_w that also carry it
+        // formats, the per-node FP32 (phi_w, p_w, ux_w, uy_w) that also carries it
         if (c->storage == STORE_F64)
             off_q += round_up(2 * I.d.plane, 64);
         else

@@ -56,7 +56,7 @@ struct StepArgs {
     void* gdst;
     void* q;
     void* phiplane;     // split step: phi of the current step
-    const void* rsrc;   // reduced formats: planes phi_w, p_w, u_w of the previous step
+    const void* rsrc;   // reduced formats: per-node (phi_w, p_w, u_w) of the previous step
     void* rdst;         // and of this step
     hipStream_t stream;
 };

@@ -12,12 +12,13 @@
 // in place instead of pulling.
 //
 // Storage.  FP64: the populations themselves, and phi u of the previous step.  FP32 /
-// FP16 ("equilibrium deviation"): every node also writes four FP32 planes, its phi_w, p_w
+// FP16 ("equilibrium deviation"): every node also writes, as one float4, its phi_w, p_w
 // and u_w (phi, p, u rounded to FP32).  An f slot holds (f_i - w_i phi_w) 2^exp_f and a g
 // slot (g_i - g^eq_i(rho(phi_w), p_w, u_w)) 2^exp_g, both taken at the node that wrote the
-// slot.  A reader decodes a pulled population with the planes of its source node, staged
-// with a two-node halo in LDS; the g equilibrium is evaluated by one function, identically
-// on both sides, and the g relaxation runs in FP64.  The stored numbers are thus the small
+// slot.  A reader decodes a pulled population with the (phi_w, p_w, u_w) of its source node,
+// staged with a two-node halo in LDS; the g equilibrium is evaluated by one function,
+// identically on both sides.  The moments, and the momentum the g relaxation must keep,
+// are formed in FP64.  The stored numbers are thus the small
 // non-equilibrium parts, a bulk at rest is stored exactly, and the short formats round
 // small values only: slowly varying states keep their small increments (a weak body
 // force, a drifting interface) instead of losing them to the rounding of full-size
@@ -617,8 +618,8 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
 // k_phi_plane instead of being recomputed.
 //
 // q: FP64 format, phi u of the previous step (2 planes, updated in place).
-// msrc / mdst: reduced formats, the planes phi_w, p_w, ux_w, uy_w of the previous step
-// (read) and of this step (written).
+// msrc / mdst: reduced formats, every node's (phi_w, p_w, ux_w, uy_w) as one float4, of the
+// previous step (read) and of this step (written).
 template <typename S, int K, bool PULL, int MODE, bool RING_FROM_PLANE, bool INTERIOR, int QF>
 __device__ __forceinline__ void step_tile(
     const InstDev& I, const TileDesc& T, const S* __restrict__ fsrc,
@@ -675,10 +676,9 @@ __device__ __forceinline__ void step_tile(
                 gy %= ny;
                 gy = gy < 0 ? gy + ny : gy;
             }
-            const int o = gy * pitch + gx;
-            const float ph = ld(mb, o);
-            const RefTerms R =
-                ref_terms(I, ph, ld(mb, plane + o), ld(mb, 2 * plane + o), ld(mb, 3 * plane + o));
+            const float4 m4 = ld((const float4*)mb, gy * pitch + gx);
+            const float ph = m4.x;
+            const RefTerms R = ref_terms(I, ph, m4.y, m4.z, m4.w);
             sq[idx] = make_float4(R.A, R.B, R.ux, R.uy);
             sw[idx] = make_float2(ph, R.H);
         }
@@ -812,11 +812,7 @@ __device__ __forceinline__ void step_tile(
                 for (int i = 0; i < QF; ++i) put_pop<MODE>(fo_b, i * plane + self, fo[i] * sf);
 #pragma unroll
                 for (int i = 0; i < 9; ++i) put_pop<MODE>(go_b, i * plane + self, go[i] * sgs);
-                float* mo = mdst + I.off_mp;
-                st(mo, self, phi);
-                st(mo, plane + self, pw[0]);
-                st(mo, 2 * plane + self, pw[1]);
-                st(mo, 3 * plane + self, pw[2]);
+                st((float4*)(mdst + I.off_mp), self, make_float4(phi, pw[0], pw[1], pw[2]));
             }
         } else {
             double* qb = q + I.off_q;
@@ -897,7 +893,8 @@ __global__ __launch_bounds__(BLOCK) void k_phi_plane(
     const int lx = threadIdx.x & (TILE_X - 1);
     const int ly = threadIdx.x >> 6;
     const S* fb = fsrc + I.off_dist;
-    const float* rb = REF ? msrc + I.off_mp : nullptr;   // phi_w plane
+    // phi_w, the first component of each node's (phi_w, p_w, ux_w, uy_w)
+    const float4* rb = REF ? (const float4*)(msrc + I.off_mp) : nullptr;
     const C isf = C(I.inv_scale_f);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -911,8 +908,8 @@ __global__ __launch_bounds__(BLOCK) void k_phi_plane(
             for (int i = 0; i < QF; ++i) v[i] = Store<S>::get(fb, o[i]);
             if (REF) {
 #pragma unroll
-                for (int i = 0; i < QF; ++i) ref[i] = rb[src[i]];
-                base = rb[y * I.pitch + x];
+                for (int i = 0; i < QF; ++i) ref[i] = rb[src[i]].x;
+                base = rb[y * I.pitch + x].x;
             }
             phiplane[I.off_phi + y * I.pitch + x] = phi_of<C, REF, QF>(v, ref, base, isf);
         }
@@ -977,11 +974,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(const InstDev* __restrict__ inst
         }
     }
     if (REF) {
-        float* mb = mp + I.off_mp;
-        mb[self] = phw;
-        mb[plane + self] = 0.0f;
-        mb[2 * plane + self] = uxw;
-        mb[3 * plane + self] = uyw;
+        ((float4*)(mp + I.off_mp))[self] = make_float4(phw, 0.0f, uxw, uyw);
     } else {
         double* qb = q + I.off_q;
         qb[self] = ph * ux;
