@@ -58,7 +58,7 @@ struct lbm_ctx {
     size_t esize = 4;          // bytes per stored distribution value
     size_t qsize = 4;          // bytes per split-kernel phi value (compute type)
     int64_t dist_elems = 0;    // elements of one distribution set (all instances, 9 planes)
-    int64_t q_elems = 0;       // FP64 phi u: 2 double planes per instance
+    int64_t q_elems = 0;       // FP64 phi u: a double2 per node and instance
     int64_t phi_elems = 0;     // split-kernel phi: 1 plane per instance
     int64_t mp_elems = 0;      // reduced formats: a float4 per node and instance
     void* f[2] = {nullptr, nullptr};

@@ -617,7 +617,7 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
 // RING_FROM_PLANE (split step): the halo ring is read from a phi plane written by
 // k_phi_plane instead of being recomputed.
 //
-// q: FP64 format, phi u of the previous step (2 planes, updated in place).
+// q: FP64 format, phi u of the previous step (one double2 per node, updated in place).
 // msrc / mdst: reduced formats, every node's (phi_w, p_w, ux_w, uy_w) as one float4, of the
 // previous step (read) and of this step (written).
 template <typename S, int K, bool PULL, int MODE, bool RING_FROM_PLANE, bool INTERIOR, int QF>
@@ -815,8 +815,10 @@ __device__ __forceinline__ void step_tile(
                 st((float4*)(mdst + I.off_mp), self, make_float4(phi, pw[0], pw[1], pw[2]));
             }
         } else {
-            double* qb = q + I.off_q;
-            double qx = qb[self], qy = qb[plane + self];
+            // phi u of the previous step, one double2 per node
+            double2* qb = (double2*)(q + I.off_q);
+            const double2 q2 = ld((const double2*)qb, self);
+            double qx = q2.x, qy = q2.y;
             const double nb[9] = {phi, r1[2], r2[1], r1[0], r0[1], r2[2], r2[0], r0[0], r0[2]};
             double fo[9], go[9];
             node_update_f64<MODE, QF>(I, f[k], g[k], nb, qx, qy, fo, go, mom);
@@ -825,8 +827,7 @@ __device__ __forceinline__ void step_tile(
                 for (int i = 0; i < QF; ++i) put_pop<MODE>(fo_b, i * plane + self, fo[i]);
 #pragma unroll
                 for (int i = 0; i < 9; ++i) put_pop<MODE>(go_b, i * plane + self, go[i]);
-                qb[self] = qx;
-                qb[plane + self] = qy;
+                st(qb, self, make_double2(qx, qy));
             }
         }
         if (MODE == MODE_MOMENTS) {
@@ -976,9 +977,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(const InstDev* __restrict__ inst
     if (REF) {
         ((float4*)(mp + I.off_mp))[self] = make_float4(phw, 0.0f, uxw, uyw);
     } else {
-        double* qb = q + I.off_q;
-        qb[self] = ph * ux;
-        qb[plane + self] = ph * uy;
+        ((double2*)(q + I.off_q))[self] = make_double2(ph * ux, ph * uy);
     }
 }
 
