@@ -103,14 +103,14 @@ def traffic_from_profile(wl, storage):
     return d.get("hbm_bytes_per_launch")
 
 
-def time_gpu(cs, storage, steps, warmup, kernel, tile_rows, final_stats=False):
+def time_gpu(cs, storage, steps, warmup, kernel, tile_rows, final_stats=False, stores="auto"):
     """Milliseconds of `steps` steps after `warmup` untimed ones.  With final_stats, also
     the first instance's L and sum(phi) drift at the end (read after the timed region)."""
     import torch
     from paper_1710_09541_amd import lbm
     stream = torch.cuda.Stream()
     sim = lbm.Simulation(cs, storage=storage, kernel=kernel, tile_rows=tile_rows,
-                         stream=stream.cuda_stream)
+                         stream=stream.cuda_stream, stores=stores)
     info = sim.info()
     s0 = sim.reduce()["sum_phi"] if final_stats else None
     sim.step(warmup)
@@ -131,10 +131,11 @@ def time_gpu(cs, storage, steps, warmup, kernel, tile_rows, final_stats=False):
     return ms, info, stats
 
 
-def measure(cs, storage, steps, warmup, kernel="auto", tile_rows=0, final_stats=False):
+def measure(cs, storage, steps, warmup, kernel="auto", tile_rows=0, final_stats=False,
+            stores="auto"):
     nodes = sum(c["nx"] * c["ny"] for c in cs)
     qf = cs[0].get("f_lattice", 9)
-    ms, info, stats = time_gpu(cs, storage, steps, warmup, kernel, tile_rows, final_stats)
+    ms, info, stats = time_gpu(cs, storage, steps, warmup, kernel, tile_rows, final_stats, stores)
     per_launch_s = ms / 1e3 / steps
     ach = alg_bytes(storage, qf) * nodes / per_launch_s / 1e9
     return {"mlups": nodes * steps / (ms / 1e3) / 1e6, "ms_per_step": ms / steps,
@@ -214,6 +215,7 @@ def main():
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--kernel", default="auto")
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--stores", default="auto", choices=["auto", "cached", "streaming"])
     ap.add_argument("--variants", default="f64,f16", help="other storages to time ('none' for none)")
     ap.add_argument("--cpu-steps", type=int, default=1500,
                     help="oracle steps of the CPU baseline (also the accuracy horizon)")
@@ -262,7 +264,7 @@ def main():
     others = [] if args.variants in ("", "none") else args.variants.split(",")
     for st in [args.storage] + [v for v in others if v and v != args.storage]:
         r = measure(cs, st, args.steps, args.warmup, args.kernel, args.tile_rows,
-                    final_stats=single)
+                    final_stats=single, stores=args.stores)
         log("%s: %.1f MLUPS, %.4f ms/step, %.0f GB/s algorithmic" % (st, r["mlups"],
                                                                       r["ms_per_step"],
                                                                       r["achieved_gbs"]))
