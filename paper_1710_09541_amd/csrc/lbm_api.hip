@@ -598,6 +598,16 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
         Instance& I = c->inst[k];
         I.p = p[k];
         fill_inst(I, c->storage, phi0[k], ux0[k], uy0[k]);
+        // the kernels address one instance's 9 planes through a buffer resource with a 32-bit
+        // byte range
+        if (9 * I.d.plane * (int64_t)c->esize >= ((int64_t)1 << 32)) {
+            char b[160];
+            snprintf(b, sizeof b, "instance %d: grid too large for one instance in this storage "
+                     "format (9 planes must stay below 4 GiB)", k);
+            const std::string m(b);
+            delete c;
+            return fail(nullptr, LBM_ERR_PARAM, m);
+        }
         I.d.off_dist = off_dist;
         I.d.off_q = off_q;
         I.d.off_phi = off_phi;

@@ -120,6 +120,53 @@ struct Store<_Float16> {
     }
 };
 
+// Buffer access to one instance's populations: a resource over its 9 planes, a per-lane byte
+// offset (the node) and a wave-uniform byte offset in a scalar register (plane i and the
+// pull shift), so the accesses of a node share one vector offset and cost no vector
+// arithmetic.  Out-of-range offsets read zero and drop writes (hardware range check).  The
+// descriptor's last word is the raw-buffer configuration of the gfx9 family.  The reduced
+// formats use it (measured: FP16 +2 to +4 %, FP32 unchanged); the FP64 format keeps 64-bit
+// global addressing, which measured 2 % faster at 1024^2.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+template <typename S>
+constexpr bool kBufAddr = sizeof(S) < 8;
+__device__ __forceinline__ Rsrc rsrc_of(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+template <typename S>
+struct Buf;
+template <>
+struct Buf<double> {
+    static __device__ __forceinline__ double get(Rsrc r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void put(Rsrc r, uint32_t vo, uint32_t so, double v) {
+        __builtin_amdgcn_raw_buffer_store_b64(
+            __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned int, v), r, vo, so, 0);
+    }
+};
+template <>
+struct Buf<float> {
+    static __device__ __forceinline__ float get(Rsrc r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void put(Rsrc r, uint32_t vo, uint32_t so, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, vo, so, 0);
+    }
+};
+template <>
+struct Buf<_Float16> {
+    static __device__ __forceinline__ float get(Rsrc r, uint32_t vo, uint32_t so) {
+        return (float)__builtin_bit_cast(_Float16,
+                                         __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void put(Rsrc r, uint32_t vo, uint32_t so, float v) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r,
+                                              vo, so, 0);
+    }
+};
+
 // f is kept as a rest deviation in every format shorter than FP64
 template <typename S>
 constexpr bool rest_deviation() {
@@ -263,13 +310,18 @@ __device__ __forceinline__ int ghost_row(const InstDev& I, int y) {
 // last-level cache and costs when it fits; the autotuner chooses.
 enum { MODE_STEP = 0, MODE_MOMENTS = 1, MODE_STEP_NT = 2 };
 
-// store of a collided population, non-temporal in MODE_STEP_NT
+// store of a collided population into plane offset po (= i * plane) at node `self`: through
+// the buffer resource r over the destination planes (reduced formats), non-temporal in
+// MODE_STEP_NT
 template <int MODE, typename S, typename C>
-__device__ __forceinline__ void put_pop(S* p, int o, C v) {
+__device__ __forceinline__ void put_pop(Rsrc r, S* p, int po, int self, C v) {
     if constexpr (MODE == MODE_STEP_NT)
-        __builtin_nontemporal_store((S)v, (S*)((char*)p + (uint32_t)o * (uint32_t)sizeof(S)));
+        __builtin_nontemporal_store(
+            (S)v, (S*)((char*)p + (uint32_t)(po + self) * (uint32_t)sizeof(S)));
+    else if constexpr (kBufAddr<S>)
+        Buf<S>::put(r, (uint32_t)self * (uint32_t)sizeof(S), (uint32_t)po * (uint32_t)sizeof(S), v);
     else
-        Store<S>::put(p, o, v);
+        Store<S>::put(p, po + self, v);
 }
 
 // ------------------------------------------------------------------ FP64 node
@@ -684,6 +736,12 @@ __device__ __forceinline__ void step_tile(
         }
     }
 
+    // slot i of a node arrives from node - c_i: away from the edges (and on the first step,
+    // which reads the node's own slots) that shift is the same for every node, and the loads
+    // of the reduced formats go through buffer resources with the shift in a scalar offset
+    constexpr bool UNIFORM = (INTERIOR || !PULL) && kBufAddr<S>;
+    const uint32_t pop_bytes = 9u * (uint32_t)plane * (uint32_t)sizeof(S);
+    const Rsrc rf = rsrc_of(fb, pop_bytes), rg = rsrc_of(gb, pop_bytes);
     C f[K][9], g[K][9];
     bool valid[K];
 #pragma unroll
@@ -692,12 +750,24 @@ __device__ __forceinline__ void step_tile(
         valid[k] = lx < w && yl < h;
         if (valid[k]) {
             const int y = T.y0 + yl;
-            int o[9], src[9];
-            pull_offsets<PULL, INTERIOR>(I, x, y, o, src);
+            if (UNIFORM) {
+                const uint32_t vo = (uint32_t)(y * pitch + x) * (uint32_t)sizeof(S);
 #pragma unroll
-            for (int i = 0; i < QF; ++i) f[k][i] = Store<S>::get(fb, o[i]);
+                for (int i = 0; i < 9; ++i) {
+                    const uint32_t so =
+                        (uint32_t)(i * plane - (PULL ? dotc<int>(i, 1, pitch) : 0)) *
+                        (uint32_t)sizeof(S);
+                    if (i < QF) f[k][i] = Buf<S>::get(rf, vo, so);
+                    g[k][i] = Buf<S>::get(rg, vo, so);
+                }
+            } else {
+                int o[9], src[9];
+                pull_offsets<PULL, INTERIOR>(I, x, y, o, src);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) g[k][i] = Store<S>::get(gb, o[i]);
+                for (int i = 0; i < QF; ++i) f[k][i] = Store<S>::get(fb, o[i]);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) g[k][i] = Store<S>::get(gb, o[i]);
+            }
         }
     }
     // halo ring: top row, bottom row (w + 2 each), left and right columns (h each); the
@@ -725,10 +795,20 @@ __device__ __forceinline__ void step_tile(
         ryraw = T.y0 + ry;
         rgy = INTERIOR ? ryraw : ghost_row(I, ryraw);
         if (!RING_FROM_PLANE) {
-            int o[9], src[9];
-            pull_offsets<PULL, INTERIOR>(I, rgx, rgy, o, src);
+            if (UNIFORM) {
+                const uint32_t vo = (uint32_t)(rgy * pitch + rgx) * (uint32_t)sizeof(S);
 #pragma unroll
-            for (int i = 0; i < QF; ++i) rfv[i] = Store<S>::get(fb, o[i]);
+                for (int i = 0; i < QF; ++i)
+                    rfv[i] = Buf<S>::get(
+                        rf, vo,
+                        (uint32_t)(i * plane - (PULL ? dotc<int>(i, 1, pitch) : 0)) *
+                            (uint32_t)sizeof(S));
+            } else {
+                int o[9], src[9];
+                pull_offsets<PULL, INTERIOR>(I, rgx, rgy, o, src);
+#pragma unroll
+                for (int i = 0; i < QF; ++i) rfv[i] = Store<S>::get(fb, o[i]);
+            }
         }
     }
     if (REF) {
@@ -779,6 +859,7 @@ __device__ __forceinline__ void step_tile(
 
     S* fo_b = fdst + I.off_dist;
     S* go_b = gdst + I.off_dist;
+    const Rsrc rfo = rsrc_of(fo_b, pop_bytes), rgo = rsrc_of(go_b, pop_bytes);
     const C sf = SCALED ? C(I.scale_f) : C(1), sgs = SCALED ? C(I.scale_g) : C(1);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -809,9 +890,9 @@ __device__ __forceinline__ void step_tile(
                                   r0[0], r0[2], res[k], qx, qy, fo, go, pw, mom);
             if (MODE != MODE_MOMENTS) {
 #pragma unroll
-                for (int i = 0; i < QF; ++i) put_pop<MODE>(fo_b, i * plane + self, fo[i] * sf);
+                for (int i = 0; i < QF; ++i) put_pop<MODE>(rfo, fo_b, i * plane, self, fo[i] * sf);
 #pragma unroll
-                for (int i = 0; i < 9; ++i) put_pop<MODE>(go_b, i * plane + self, go[i] * sgs);
+                for (int i = 0; i < 9; ++i) put_pop<MODE>(rgo, go_b, i * plane, self, go[i] * sgs);
                 st((float4*)(mdst + I.off_mp), self, make_float4(phi, pw[0], pw[1], pw[2]));
             }
         } else {
@@ -824,9 +905,9 @@ __device__ __forceinline__ void step_tile(
             node_update_f64<MODE, QF>(I, f[k], g[k], nb, qx, qy, fo, go, mom);
             if (MODE != MODE_MOMENTS) {
 #pragma unroll
-                for (int i = 0; i < QF; ++i) put_pop<MODE>(fo_b, i * plane + self, fo[i]);
+                for (int i = 0; i < QF; ++i) put_pop<MODE>(rfo, fo_b, i * plane, self, fo[i]);
 #pragma unroll
-                for (int i = 0; i < 9; ++i) put_pop<MODE>(go_b, i * plane + self, go[i]);
+                for (int i = 0; i < 9; ++i) put_pop<MODE>(rgo, go_b, i * plane, self, go[i]);
                 st(qb, self, make_double2(qx, qy));
             }
         }
