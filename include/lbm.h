@@ -117,7 +117,7 @@ typedef struct {
     int32_t storage;          /* LBM_STORE_*, the same for every instance */
     int32_t kernel;           /* LBM_KERNEL_* */
     int32_t tile_rows;        /* rows per fused-kernel tile (4, 8 or 16); 0 = autotune/default */
-    int32_t use_graph;        /* 1: lbm_step replays captured HIP graphs of two steps */
+    int32_t use_graph;        /* 1: lbm_step replays captured HIP graphs of 64, 16 and 2 steps */
     int32_t check_every;      /* > 0: every that many steps lbm_step checks for non-finite
                                  values and returns LBM_ERR_NONFINITE (synchronises) */
     int32_t stores;           /* LBM_STORES_* (with kernel / tile_rows AUTO or 0 the choice is

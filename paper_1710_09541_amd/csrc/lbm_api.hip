@@ -25,6 +25,12 @@ thread_local std::string g_thread_err;
 
 constexpr uint64_t STATE_MAGIC = 0x4c424d5046534154ull;  // "LBMPFSAT"
 constexpr int STATE_VERSION = 3;
+// steps per captured graph, shortest first: each graph launch costs a few microseconds
+// between the last kernel of one graph and the first of the next, which long graphs spread
+// over more steps (measured: 64 steps per graph 0.6 % faster than 16 at 1024^2 FP32 and 4 %
+// on a 64^2 grid; 256 no faster than 64)
+constexpr int NGRAPH = 3;
+constexpr int GRAPH_STEPS[NGRAPH] = {2, 16, 64};
 constexpr int PLANE_PAD = 192;  // elements added to each plane: breaks power-of-two plane strides
 
 struct Instance {
@@ -79,7 +85,7 @@ struct lbm_ctx {
     hipStream_t cap_stream = nullptr;
     // captured step sequences starting from buffer 0 / 1: graph[g][from] holds
     // GRAPH_STEPS[g] consecutive steps (an even number, so the buffer parity returns)
-    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraphExec_t graph[NGRAPH][2] = {};
     int cur = 0;               // buffer holding the current state
     bool streamed = true;      // the current state is still the initial, streamed one
     int64_t step = 0;
@@ -221,7 +227,7 @@ std::vector<TileDesc> build_tiles(const std::vector<Instance>& v, int rows) {
 
 void free_all(lbm_ctx* c) {
     for (int i = 0; i < 2; ++i) {
-        for (int g = 0; g < 2; ++g) {
+        for (int g = 0; g < NGRAPH; ++g) {
             if (c->graph[g][i]) hipGraphExecDestroy(c->graph[g][i]);
             c->graph[g][i] = nullptr;
         }
@@ -281,16 +287,12 @@ int launch_one(lbm_ctx* c, hipStream_t st) {
 }
 
 void drop_graphs(lbm_ctx* c) {
-    for (int g = 0; g < 2; ++g)
+    for (int g = 0; g < NGRAPH; ++g)
         for (int i = 0; i < 2; ++i) {
             if (c->graph[g][i]) hipGraphExecDestroy(c->graph[g][i]);
             c->graph[g][i] = nullptr;
         }
 }
-
-// steps per captured graph: a short one and a long one (fewer launches per step, which is
-// what bounds small grids)
-constexpr int GRAPH_STEPS[2] = {2, 16};
 
 // captures GRAPH_STEPS[g] consecutive steps starting from buffer `from`
 int capture_steps(lbm_ctx* c, int g, int from) {
@@ -419,7 +421,7 @@ void tune_cache_store(const lbm_ctx* c, const std::string& key) {
 // is left untouched.  (The alternation matters: the buffer a step reads was written by the
 // step before, partly still in the last-level cache.)  If the temporary cannot be
 // allocated, the launches repeat from the current buffer into the spare one.  The fastest
-// median of interleaved rounds wins, by a margin of 2 % over smaller tiles.
+// median of interleaved rounds wins, by a margin of 1 % over smaller tiles.
 int autotune(lbm_ctx* c) {
     struct Cand {
         int kernel, rows;
@@ -528,13 +530,13 @@ int autotune(lbm_ctx* c) {
     }
     if (rc == LBM_OK) {
         // candidates come smallest tile first, cached stores before streaming ones; a later
-        // one must win by more than 2 %, so run-to-run noise does not flip the choice between
-        // near-equal configurations
+        // one must win by more than 1 % (several times the spread of a candidate's timed
+        // rounds), so noise does not flip the choice between near-equal configurations
         float best = 1e30f;
         for (int ci = 0; ci < nc; ++ci) {
             float* tc = t.data() + (size_t)ci * NREP;
             std::sort(tc, tc + NREP);
-            if (tc[NREP / 2] < 0.98f * best) {
+            if (tc[NREP / 2] < 0.99f * best) {
                 best = tc[NREP / 2];
                 c->kernel = cands[ci].kernel;
                 c->tile_rows = cands[ci].rows;
@@ -762,7 +764,8 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
         int64_t done = 0;
         while (done < chunk) {
             if (!c->streamed && c->opt.use_graph && chunk - done >= GRAPH_STEPS[0]) {
-                const int g = chunk - done >= GRAPH_STEPS[1] ? 1 : 0;
+                int g = NGRAPH - 1;
+                while (chunk - done < GRAPH_STEPS[g]) --g;
                 if (!c->graph[g][c->cur]) {
                     int rc = capture_steps(c, g, c->cur);
                     if (rc) return rc;
