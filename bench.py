@@ -184,6 +184,18 @@ def poiseuille_parity(storage, ref_cache):
                                (storage == "f16" or e["phi"] <= TOL[storage]))}
 
 
+def host_cpu():
+    """Model name of this host's CPU, as /proc/cpuinfo gives it."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(c, steps):
     """The FP64 oracle timed on this host's cores over a bounded sample of the workload."""
     from oracle.oracle import OracleSim
@@ -200,7 +212,7 @@ def cpu_baseline(c, steps):
     nodes = c["nx"] * c["ny"]
     ref = s.moments()
     return {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": min(cores, threads),
-            "kind": "oracle",
+            "kind": "oracle", "host": host_cpu(),
             "sample": "%dx%d spinodal, %d steps after 1 untimed step, FP64, OpenMP over rows "
                       "(%d threads), %.1f s" % (c["nx"], c["ny"], steps, min(cores, threads), dt)
             }, ref
