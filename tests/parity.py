@@ -35,6 +35,15 @@ def errors(case, got, ref):
     return e
 
 
+def perturbed(case, steps, eps=1e-7, seed=5):
+    """The oracle's moments after `steps` from phi0 perturbed by relative noise of size eps."""
+    rng = np.random.default_rng(seed)
+    phi = case["phi0"] * (1.0 + eps * rng.standard_normal(case["phi0"].shape))
+    s = OracleSim(case, phi, case["ux0"], case["uy0"])
+    s.step(steps)
+    return s.moments()
+
+
 def sensitivity(case, steps, eps=1e-7, seed=5):
     """Errors of the oracle against itself when phi0 is perturbed by relative noise of size
     eps (about the rounding of a 32-bit store).  Where the interface normal is taken at a

@@ -9,7 +9,7 @@ import pytest
 
 from oracle import diag
 from paper_1710_09541_amd import cases, lbm
-from tests.parity import TOL, errors, report, run_hip, run_oracle, sensitivity
+from tests.parity import TOL, errors, perturbed, report, run_hip, run_oracle, sensitivity
 
 pytestmark = pytest.mark.gpu
 
@@ -84,6 +84,61 @@ def test_spinodal_full_size_f64_autotuned():
     """1024 x 1024 spinodal at full size through the autotuned fused kernel, FP64 storage,
     5 steps (the same tile loop, indexing and block order as the FP32 benchmark)."""
     _check("spinodal 1024^2", cases.spinodal(1024, seed=0), 5, "f64", kernel="auto")
+
+
+@pytest.mark.parametrize("storage,steps", [("f32", 2), ("f32", 50), ("f16", 2), ("f16", 50)])
+def test_spinodal_full_size_reduced_vs_oracle(storage, steps):
+    """The benchmarked workload itself: 1024 x 1024 spinodal in the launch configuration
+    the benchmark times (autotuned kernel, tile height and stores, graph replay), every node
+    against the oracle.  The random initial field has nodes of nearly vanishing grad phi,
+    where the direction of n is set by rounding: the oracle itself, with phi0 perturbed by
+    relative noise of 1e-7 (FP32 rounding), moves phi by 4e-5 after one step and 1.4e-2
+    after 50.  For FP16 storage the noise is 5e-7: the size at which the oracle's u departs
+    after 2 steps as far as the FP16 format's does (1.5e-5).
+    * Whole field: each field within the storage tolerance or 4x the oracle's spread under
+      that noise, whichever is larger.
+    * After 2 steps, nodes where the noise is not amplified (the perturbed oracle moves phi
+      and u by less than 10x the noise), less a margin of `steps` + 2 nodes around the
+      amplified ones (about 8 % of the grid): phi and u within the storage tolerance (u only
+      for FP16).  By 50 steps the amplified regions cover the grid."""
+    eps = {"f32": 1e-7, "f16": 5e-7}[storage]
+    c = cases.spinodal(1024, seed=0)
+    ref = run_oracle(c, steps)
+    got = run_hip(c, steps, storage, kernel="auto", stores="auto", use_graph=True)
+    e = errors(c, got, ref)
+    report("spinodal 1024^2 %d steps" % steps, storage, e)
+    pert = perturbed(c, steps, eps=eps)
+    sens = errors(c, pert, ref)
+    fields = ("phi", "u", "p") if storage == "f32" else ("u",)
+    for f in fields:
+        bound = max(TOL[storage], 4 * sens[f])
+        print("[parity]   %s: error %.2e, oracle spread %.2e, bound %.2e" % (f, e[f], sens[f], bound),
+              flush=True)
+        assert e[f] <= bound, (storage, steps, f, e[f], bound)
+    if steps > 2:
+        return
+    u_ref = np.sqrt(ref["ux"] ** 2 + ref["uy"] ** 2)
+    scale_u = max(float(u_ref.max()), c["u_scale"])
+    moved = np.abs(pert["phi"] - ref["phi"]) > 10 * eps
+    for k in ("ux", "uy"):
+        moved |= np.abs(pert[k] - ref[k]) > 10 * eps * scale_u
+    # the nodes an amplified difference can reach (one node per step, periodic grid)
+    for _ in range(steps + 2):
+        grown = moved.copy()
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                grown |= np.roll(moved, (dy, dx), axis=(0, 1))
+        moved = grown
+    calm = ~moved
+    e_phi = float(np.max(np.abs(got["phi"] - ref["phi"])[calm]))
+    e_u = max(float(np.max(np.abs(got["ux"] - ref["ux"])[calm])),
+              float(np.max(np.abs(got["uy"] - ref["uy"])[calm]))) / scale_u
+    print("[parity]   well-conditioned nodes: %.1f %%, phi %.2e, u %.2e"
+          % (100.0 * calm.mean(), e_phi, e_u), flush=True)
+    assert calm.mean() > 0.02, calm.mean()
+    if storage == "f32":
+        assert e_phi <= TOL[storage], e_phi
+    assert e_u <= TOL[storage], e_u
 
 
 def test_spinodal_f64_100_steps():
