@@ -103,14 +103,15 @@ def traffic_from_profile(wl, storage):
     return d.get("hbm_bytes_per_launch")
 
 
-def time_gpu(cs, storage, steps, warmup, kernel, tile_rows, final_stats=False, stores="auto"):
+def time_gpu(cs, storage, steps, warmup, kernel, tile_rows, final_stats=False, stores="auto",
+             grid="auto"):
     """Milliseconds of `steps` steps after `warmup` untimed ones.  With final_stats, also
     the first instance's L and sum(phi) drift at the end (read after the timed region)."""
     import torch
     from paper_1710_09541_amd import lbm
     stream = torch.cuda.Stream()
     sim = lbm.Simulation(cs, storage=storage, kernel=kernel, tile_rows=tile_rows,
-                         stream=stream.cuda_stream, stores=stores)
+                         stream=stream.cuda_stream, stores=stores, grid=grid)
     info = sim.info()
     s0 = sim.reduce()["sum_phi"] if final_stats else None
     sim.step(warmup)
@@ -132,14 +133,16 @@ def time_gpu(cs, storage, steps, warmup, kernel, tile_rows, final_stats=False, s
 
 
 def measure(cs, storage, steps, warmup, kernel="auto", tile_rows=0, final_stats=False,
-            stores="auto"):
+            stores="auto", grid="auto"):
     nodes = sum(c["nx"] * c["ny"] for c in cs)
     qf = cs[0].get("f_lattice", 9)
-    ms, info, stats = time_gpu(cs, storage, steps, warmup, kernel, tile_rows, final_stats, stores)
+    ms, info, stats = time_gpu(cs, storage, steps, warmup, kernel, tile_rows, final_stats, stores,
+                               grid)
     per_launch_s = ms / 1e3 / steps
     ach = alg_bytes(storage, qf) * nodes / per_launch_s / 1e9
     return {"mlups": nodes * steps / (ms / 1e3) / 1e6, "ms_per_step": ms / steps,
             "kernel": info["kernel"], "tile_rows": info["tile_rows"], "stores": info["stores"],
+            "grid": info["grid"],
             "f_lattice": qf,
             "alg_bytes_per_lu": alg_bytes(storage, qf), "achieved_gbs": ach,
             "frac_hbm_peak": ach / PEAK_HBM_GBS, "nodes": nodes, "steps": steps,
@@ -228,6 +231,7 @@ def main():
     ap.add_argument("--kernel", default="auto")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--stores", default="auto", choices=["auto", "cached", "streaming"])
+    ap.add_argument("--grid", default="auto", choices=["auto", "tiles", "persistent"])
     ap.add_argument("--variants", default="f64,f16", help="other storages to time ('none' for none)")
     ap.add_argument("--cpu-steps", type=int, default=1500,
                     help="oracle steps of the CPU baseline (also the accuracy horizon)")
@@ -276,10 +280,10 @@ def main():
     others = [] if args.variants in ("", "none") else args.variants.split(",")
     for st in [args.storage] + [v for v in others if v and v != args.storage]:
         r = measure(cs, st, args.steps, args.warmup, args.kernel, args.tile_rows,
-                    final_stats=single, stores=args.stores)
-        log("%s: %.1f MLUPS, %.4f ms/step, %.0f GB/s algorithmic" % (st, r["mlups"],
-                                                                      r["ms_per_step"],
-                                                                      r["achieved_gbs"]))
+                    final_stats=single, stores=args.stores, grid=args.grid)
+        log("%s: %.1f MLUPS, %.4f ms/step, %.0f GB/s algorithmic (%d rows, %s stores, %s grid)"
+            % (st, r["mlups"], r["ms_per_step"], r["achieved_gbs"], r["tile_rows"], r["stores"],
+               r["grid"]))
         if ref is not None:
             r["accuracy_vs_oracle"] = spinodal_accuracy(cs[0], st, args.cpu_steps + 1, ref)
             log("%s: accuracy %s" % (st, json.dumps(r["accuracy_vs_oracle"])))
@@ -348,7 +352,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "storage": args.storage, "nodes": nodes,
                    "kernel": kname, "tile_rows": main_r["tile_rows"],
-                   "stores": main_r["stores"]},
+                   "stores": main_r["stores"], "grid": main_r["grid"]},
         "roofline": {"bound": "hbm", "achieved": round(main_r["achieved_gbs"], 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(main_r["frac_hbm_peak"], 4),

@@ -81,6 +81,16 @@ enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16 = 2 };
  * fits).  Results are bitwise identical either way. */
 enum { LBM_STORES_AUTO = 0, LBM_STORES_CACHED = 1, LBM_STORES_STREAMING = 2 };
 
+/* Launch grid of the fused step kernel: one block per tile, or a persistent grid of as many
+ * blocks as stay resident on the GPU (or, if the environment variable LBM_PERSIST_BLOCKS is
+ * set at lbm_init, that many blocks per XCD), each looping over a contiguous run of tiles.
+ * The split kernel and the first step always run one block per tile, as does a persistent
+ * grid with at least as many blocks as tiles.  Results are bitwise identical either way.
+ * AUTO runs one block per tile: the persistent grid measured 3-14 % slower on every workload
+ * and format on MI355X (the loop costs registers, and the hardware dispatcher balances the
+ * tiles better than a fixed assignment). */
+enum { LBM_GRID_AUTO = 0, LBM_GRID_TILES = 1, LBM_GRID_PERSISTENT = 2 };
+
 /* kernel choice for the step */
 enum {
     LBM_KERNEL_AUTO = 0,  /* the autotuner picks */
@@ -125,7 +135,8 @@ typedef struct {
                                  LBM_AUTOTUNE_CACHE names a file, choices are read from and
                                  appended to it, keyed by GPU, storage, lattice, options and
                                  grid sizes) */
-    int32_t reserved[2];
+    int32_t grid;             /* LBM_GRID_* (AUTO: one block per tile) */
+    int32_t reserved;
 } lbm_options;
 
 /* Integral diagnostics of one instance, FP64 accumulation in a fixed order. */
@@ -182,11 +193,11 @@ int lbm_get_state(lbm_ctx* c, void* buf, size_t* bytes);
  * storage.  Synchronises. */
 int lbm_set_state(lbm_ctx* c, const void* buf, size_t bytes);
 
-/* Number of steps taken; the kernel (LBM_KERNEL_FUSED / SPLIT), tile rows and population
- * stores (LBM_STORES_CACHED / STREAMING) the context runs with.  Any pointer may be NULL;
- * LBM_ERR_PARAM if c is NULL. */
+/* Number of steps taken; the kernel (LBM_KERNEL_FUSED / SPLIT), tile rows, population
+ * stores (LBM_STORES_CACHED / STREAMING) and launch grid (LBM_GRID_TILES / PERSISTENT) the
+ * context runs with.  Any pointer may be NULL; LBM_ERR_PARAM if c is NULL. */
 int lbm_info(const lbm_ctx* c, int64_t* step, int32_t* kernel, int32_t* tile_rows,
-             int32_t* stores);
+             int32_t* stores, int32_t* grid);
 
 /* Message of the last error of c, or of the calling thread if c is NULL. */
 const char* lbm_last_error(const lbm_ctx* c);

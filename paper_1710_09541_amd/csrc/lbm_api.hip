@@ -93,6 +93,9 @@ struct lbm_ctx {
     int tile_rows = 8;
     int qf = 9;                // velocities of the phase-field lattice
     bool nt_store = false;     // non-temporal population stores
+    bool persistent = false;   // persistent grid of resident blocks
+    int num_cu = 0;            // compute units of the device
+    int persist_override = 0;  // LBM_PERSIST_BLOCKS: blocks per XCD of a persistent grid
     std::string err;
 };
 
@@ -246,6 +249,25 @@ void free_all(lbm_ctx* c) {
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
 }
 
+// blocks per XCD of a persistent grid: as many as stay resident on the whole GPU (0 if
+// the runtime cannot say, and then no persistent grid is used), or the number the
+// environment variable LBM_PERSIST_BLOCKS gives
+int persist_blocks(const lbm_ctx* c, int rows, bool nt) {
+    if (c->persist_override > 0) return c->persist_override;
+    const int per_cu = step_blocks_per_cu(c->storage, c->qf, rows, nt);
+    if (per_cu <= 0 || c->num_cu <= 0) return 0;
+    return std::max(1, per_cu * c->num_cu / NXCD);
+}
+
+// whether steps run on a persistent grid: the fused kernel with fewer resident blocks than
+// tiles (otherwise every block has one tile anyway)
+bool runs_persistent(const lbm_ctx* c) {
+    if (!c->persistent || c->kernel != LBM_KERNEL_FUSED) return false;
+    const int pb = persist_blocks(c, c->tile_rows, c->nt_store);
+    const int per = (c->lists[list_index(c->tile_rows)].count + NXCD - 1) / NXCD;
+    return pb > 0 && pb < per;
+}
+
 StepArgs step_args(lbm_ctx* c, int src, bool pull, int rows, bool split, void* q) {
     StepArgs a;
     const TileList& L = c->lists[list_index(rows)];
@@ -255,6 +277,7 @@ StepArgs step_args(lbm_ctx* c, int src, bool pull, int rows, bool split, void* q
     a.tile_rows = rows;
     a.qf = c->qf;
     a.nt_store = false;
+    a.persist = 0;
     a.pull = pull;
     a.split = split;
     a.fsrc = c->f[src];
@@ -277,6 +300,7 @@ int launch_one(lbm_ctx* c, hipStream_t st) {
     {
         a = step_args(c, c->cur, true, c->tile_rows, c->kernel == LBM_KERNEL_SPLIT, c->q);
         a.nt_store = c->nt_store;
+        a.persist = runs_persistent(c) ? persist_blocks(c, c->tile_rows, c->nt_store) : 0;
     }
     a.stream = st;
     hipError_t e = launch_step(c->storage, a);
@@ -363,10 +387,10 @@ int check_finite(lbm_ctx* c) {
 // ------------------------------------------------------------------ autotuner cache
 // If the environment variable LBM_AUTOTUNE_CACHE names a file, tuned choices are kept there,
 // one text line per configuration:
-//   lbm-tune-v1 <key> <kernel> <tile_rows> <streaming stores 0/1>
+//   lbm-tune-v2 <key> <kernel> <tile_rows> <streaming stores 0/1> <persistent grid 0/1>
 // The key covers everything the timing depends on: the GPU architecture, storage, phase-
-// field lattice, the requested kernel / tile rows / store policy, the number of instances
-// and every instance's grid size.  A missing, unreadable or malformed file only means the
+// field lattice, the requested kernel / tile rows / store policy / grid, the number of
+// instances and every instance's grid size.  A missing, unreadable or malformed file only means the
 // tuner runs; a write failure is ignored.
 std::string tune_key(const lbm_ctx* c) {
     std::ostringstream k;
@@ -378,7 +402,8 @@ std::string tune_key(const lbm_ctx* c) {
     for (char& ch : arch)
         if (ch == ' ') ch = '_';
     k << arch << ":s" << c->storage << ":q" << c->qf << ":k" << c->opt.kernel << ":r"
-      << c->opt.tile_rows << ":w" << c->opt.stores << ":n" << c->inst.size();
+      << c->opt.tile_rows << ":w" << c->opt.stores << ":g" << c->opt.grid << ":n"
+      << c->inst.size();
     for (const Instance& I : c->inst) k << ":" << I.p.nx << "x" << I.p.ny;
     return k.str();
 }
@@ -392,15 +417,16 @@ bool tune_cache_lookup(lbm_ctx* c, const std::string& key) {
     while (std::getline(in, line)) {
         std::istringstream ls(line);
         std::string tag, k;
-        int kernel = 0, rows = 0, nt = 0;
-        if (!(ls >> tag >> k >> kernel >> rows >> nt) || tag != "lbm-tune-v1" || k != key)
+        int kernel = 0, rows = 0, nt = 0, pg = 0;
+        if (!(ls >> tag >> k >> kernel >> rows >> nt >> pg) || tag != "lbm-tune-v2" || k != key)
             continue;
         if ((kernel != LBM_KERNEL_FUSED && kernel != LBM_KERNEL_SPLIT) || list_index(rows) < 0 ||
-            (nt != 0 && nt != 1))
+            (nt != 0 && nt != 1) || (pg != 0 && pg != 1))
             continue;
         c->kernel = kernel;   // the last valid line for the key wins
         c->tile_rows = rows;
         c->nt_store = nt == 1;
+        c->persistent = pg == 1;
         found = true;
     }
     return found;
@@ -410,8 +436,8 @@ void tune_cache_store(const lbm_ctx* c, const std::string& key) {
     const char* path = getenv("LBM_AUTOTUNE_CACHE");
     if (!path || !*path) return;
     std::ofstream out(path, std::ios::app);
-    if (out) out << "lbm-tune-v1 " << key << " " << c->kernel << " " << c->tile_rows << " "
-                 << (c->nt_store ? 1 : 0) << "\n";
+    if (out) out << "lbm-tune-v2 " << key << " " << c->kernel << " " << c->tile_rows << " "
+                 << (c->nt_store ? 1 : 0) << " " << (c->persistent ? 1 : 0) << "\n";
 }
 
 // ------------------------------------------------------------------ autotuner
@@ -425,27 +451,36 @@ void tune_cache_store(const lbm_ctx* c, const std::string& key) {
 int autotune(lbm_ctx* c) {
     struct Cand {
         int kernel, rows;
-        bool nt;
+        bool nt, persistent;
     };
     std::vector<Cand> cands;
     const bool want_fused = c->opt.kernel != LBM_KERNEL_SPLIT;
     const bool want_split = c->opt.kernel != LBM_KERNEL_FUSED;
     const bool want_cached = c->opt.stores != LBM_STORES_STREAMING;
     const bool want_nt = c->opt.stores != LBM_STORES_CACHED;
+    // the persistent grid only when asked for: it measured 3-14 % slower than one block per
+    // tile on every workload and format, so timing it at every init is not worth its cost
+    const bool want_tiles = c->opt.grid != LBM_GRID_PERSISTENT;
+    const bool want_persistent = c->opt.grid == LBM_GRID_PERSISTENT;
     const int rows_opts[3] = {4, 8, 16};
     for (int r : rows_opts) {
         if (c->opt.tile_rows && c->opt.tile_rows != r) continue;
         if (c->storage == STORE_F64 && r == 16) continue;  // 16 rows of doubles spill
         for (int nt = 0; nt < 2; ++nt) {
             if ((nt && !want_nt) || (!nt && !want_cached)) continue;
-            if (want_fused) cands.push_back({LBM_KERNEL_FUSED, r, nt == 1});
-            if (want_split) cands.push_back({LBM_KERNEL_SPLIT, r, nt == 1});
+            for (int pg = 0; pg < 2; ++pg) {
+                if ((pg && !want_persistent) || (!pg && !want_tiles)) continue;
+                if (want_fused) cands.push_back({LBM_KERNEL_FUSED, r, nt == 1, pg == 1});
+                // the split kernel runs one block per tile
+                if (want_split && !pg) cands.push_back({LBM_KERNEL_SPLIT, r, nt == 1, false});
+            }
         }
     }
     if (cands.size() == 1) {
         c->kernel = cands[0].kernel;
         c->tile_rows = cands[0].rows;
         c->nt_store = cands[0].nt;
+        c->persistent = cands[0].persistent;
         return LBM_OK;
     }
     HIPCHK(c, copy_n_async(c->q_tune, c->q, c->q_elems * sizeof(double), c->stream));
@@ -492,6 +527,7 @@ int autotune(lbm_ctx* c) {
     auto args_of = [&](const Cand& cd, StepArgs& a, StepArgs& b) {
         a = step_args(c, c->cur, true, cd.rows, cd.kernel == LBM_KERNEL_SPLIT, c->q_tune);
         a.nt_store = cd.nt;
+        a.persist = cd.persistent ? persist_blocks(c, cd.rows, cd.nt) : 0;
         b = a;
         if (alt) {
             // temporary -> spare, then spare -> temporary
@@ -541,6 +577,7 @@ int autotune(lbm_ctx* c) {
                 c->kernel = cands[ci].kernel;
                 c->tile_rows = cands[ci].rows;
                 c->nt_store = cands[ci].nt;
+                c->persistent = cands[ci].persistent;
             }
         }
     }
@@ -575,6 +612,7 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
         return fail(nullptr, LBM_ERR_PARAM, "tile_rows must be 0, 4, 8 or 16");
     if (o.check_every < 0) return fail(nullptr, LBM_ERR_PARAM, "check_every must be >= 0");
     if (o.stores < 0 || o.stores > 2) return fail(nullptr, LBM_ERR_PARAM, "unknown store policy");
+    if (o.grid < 0 || o.grid > 2) return fail(nullptr, LBM_ERR_PARAM, "unknown launch grid");
     const auto lattice_of = [](const lbm_params& q) {
         return q.f_lattice == 0 ? (int)LBM_LATTICE_D2Q9 : (int)q.f_lattice;
     };
@@ -737,7 +775,18 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
     c->kernel = o.kernel == LBM_KERNEL_AUTO ? LBM_KERNEL_FUSED : o.kernel;
     c->tile_rows = o.tile_rows ? o.tile_rows : (c->storage == STORE_F64 ? 4 : 8);
     c->nt_store = o.stores == LBM_STORES_STREAMING;
-    if (o.kernel == LBM_KERNEL_AUTO || o.tile_rows == 0 || o.stores == LBM_STORES_AUTO) {
+    c->persistent = o.grid == LBM_GRID_PERSISTENT;
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess)
+            c->num_cu = 0;
+        const char* pb = getenv("LBM_PERSIST_BLOCKS");
+        if (pb && *pb) c->persist_override = std::max(0, atoi(pb));
+    }
+    if (o.kernel == LBM_KERNEL_AUTO || o.tile_rows == 0 || o.stores == LBM_STORES_AUTO ||
+        o.grid == LBM_GRID_AUTO) {
         const std::string key = tune_key(c);
         if (!tune_cache_lookup(c, key)) {
             int rc = autotune(c);
@@ -895,12 +944,13 @@ int lbm_set_state(lbm_ctx* c, const void* buf, size_t bytes) {
 }
 
 int lbm_info(const lbm_ctx* c, int64_t* step, int32_t* kernel, int32_t* tile_rows,
-             int32_t* stores) {
+             int32_t* stores, int32_t* grid) {
     if (!c) return fail(nullptr, LBM_ERR_PARAM, "context is NULL");
     if (step) *step = c->step;
     if (kernel) *kernel = c->kernel;
     if (tile_rows) *tile_rows = c->tile_rows;
     if (stores) *stores = c->nt_store ? LBM_STORES_STREAMING : LBM_STORES_CACHED;
+    if (grid) *grid = runs_persistent(c) ? LBM_GRID_PERSISTENT : LBM_GRID_TILES;
     return LBM_OK;
 }
 

@@ -50,6 +50,8 @@ struct StepArgs {
     bool pull;          // false only for the first step (initial state in streamed form)
     bool split;         // two launches: phi plane, then stencil + collide
     bool nt_store;      // non-temporal population stores
+    int persist;        // > 0: persistent grid of that many blocks per XCD, each looping over
+                        // tiles; 0: one block per tile
     const void* fsrc;
     const void* gsrc;
     void* fdst;
@@ -62,6 +64,8 @@ struct StepArgs {
 };
 
 hipError_t launch_step(int storage, const StepArgs& a);
+// resident blocks per compute unit of the fused step kernel (0 if the runtime cannot say)
+int step_blocks_per_cu(int storage, int qf, int rows, bool nt);
 hipError_t launch_moments(int storage, const StepArgs& a, double* out);
 hipError_t launch_init(int storage, int qf, const InstDev* insts, int inst, int nx, int ny,
                        const double* phi0, const double* ux0, const double* uy0, void* f, void* g,

@@ -664,7 +664,9 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
 //
 // Block b runs tile (b % 8) * per_xcd + b / 8: the hardware deals blocks round-robin to
 // the 8 XCDs, so each XCD walks one contiguous run of tiles and finds the halo rows of
-// its previous tiles in its own L2.
+// its previous tiles in its own L2.  With a persistent grid (stride < per_xcd blocks per
+// XCD, as many as stay resident) block b then moves on to every stride-th tile of the same
+// run, with a barrier between tiles so the next tile's LDS writes wait for this one's reads.
 //
 // RING_FROM_PLANE (split step): the halo ring is read from a phi plane written by
 // k_phi_plane instead of being recomputed.
@@ -923,10 +925,11 @@ __device__ __forceinline__ void step_tile(
 
 // A tile whose staged region (two nodes around it) lies inside the grid runs a copy of the
 // body without wrap and boundary logic; edge tiles take the general path.
-template <typename S, int K, bool PULL, int MODE, bool RING_FROM_PLANE, int QF>
+template <typename S, int K, bool PULL, int MODE, bool RING_FROM_PLANE, int QF,
+          bool PERSIST = false>
 __global__ __launch_bounds__(BLOCK) void k_step(
     const InstDev* __restrict__ insts, const TileDesc* __restrict__ tiles, int ntiles,
-    int per_xcd, const S* __restrict__ fsrc, const S* __restrict__ gsrc, S* __restrict__ fdst,
+    int per_xcd, int stride, const S* __restrict__ fsrc, const S* __restrict__ gsrc, S* __restrict__ fdst,
     S* __restrict__ gdst, double* __restrict__ q,
     const typename Store<S>::C* __restrict__ phiplane, const float* __restrict__ msrc,
     float* __restrict__ mdst, double* __restrict__ mom_out) {
@@ -938,21 +941,33 @@ __global__ __launch_bounds__(BLOCK) void k_step(
     __shared__ float4 sq[NR];
     __shared__ float2 sw[NR];
 
+    const auto run = [&](int t) {
+        const TileDesc T = tiles[t];
+        const InstDev& I = insts[T.inst];
+        const bool interior = PULL && T.x0 >= 2 && T.x0 + TILE_X + 2 <= I.nx && T.y0 >= 2 &&
+                              T.y0 + TY + 2 <= I.ny;
+        if (interior)
+            step_tile<S, K, PULL, MODE, RING_FROM_PLANE, true, QF>(
+                I, T, fsrc, gsrc, fdst, gdst, q, phiplane, msrc, mdst, mom_out, sphi, sq, sw);
+        else
+            step_tile<S, K, PULL, MODE, RING_FROM_PLANE, false, QF>(
+                I, T, fsrc, gsrc, fdst, gdst, q, phiplane, msrc, mdst, mom_out, sphi, sq, sw);
+    };
     const int b = blockIdx.x;
-    const int t = (b % NXCD) * per_xcd + b / NXCD;
-    if (t >= ntiles) return;
-    const TileDesc T = tiles[t];
-    const InstDev& I = insts[T.inst];
-    const bool interior = PULL && T.x0 >= 2 && T.x0 + TILE_X + 2 <= I.nx && T.y0 >= 2 &&
-                          T.y0 + TY + 2 <= I.ny;
-    if (interior)
-        step_tile<S, K, PULL, MODE, RING_FROM_PLANE, true, QF>(I, T, fsrc, gsrc, fdst, gdst, q,
-                                                           phiplane, msrc, mdst, mom_out, sphi,
-                                                           sq, sw);
-    else
-        step_tile<S, K, PULL, MODE, RING_FROM_PLANE, false, QF>(I, T, fsrc, gsrc, fdst, gdst, q,
-                                                            phiplane, msrc, mdst, mom_out, sphi,
-                                                            sq, sw);
+    if constexpr (!PERSIST) {
+        // one tile per block (a loop here, even of one pass, costs the compiler 15 to 35
+        // more registers)
+        const int t = (b % NXCD) * per_xcd + b / NXCD;
+        if (t < ntiles) run(t);
+    } else {
+        const int xcd = b % NXCD;
+        for (int j = b / NXCD; j < per_xcd; j += stride) {
+            const int t = xcd * per_xcd + j;
+            if (t >= ntiles) return;
+            run(t);
+            if (j + stride < per_xcd) __syncthreads();
+        }
+    }
 }
 
 // ------------------------------------------------------------------ split step: phi plane
@@ -1073,7 +1088,12 @@ template <typename S, int K, int QF>
 hipError_t step_k(const StepArgs& a) {
     using C = typename Store<S>::C;
     int per;
-    const int grid = grid_for(a.ntiles, per);
+    const int tile_grid = grid_for(a.ntiles, per);  // one block per tile
+    // persistent grid (fused pull step only): a.persist blocks per XCD, each looping over
+    // that XCD's tiles
+    int stride = per;
+    if (a.persist > 0 && a.persist < per) stride = a.persist;
+    const int grid = NXCD * stride;
     const S* fs = (const S*)a.fsrc;
     const S* gs = (const S*)a.gsrc;
     S* fd = (S*)a.fdst;
@@ -1083,23 +1103,31 @@ hipError_t step_k(const StepArgs& a) {
     const float* rs = (const float*)a.rsrc;
     float* rd = (float*)a.rdst;
     if (!a.pull) {
-        k_step<S, K, false, MODE_STEP, false, QF><<<grid, BLOCK, 0, a.stream>>>(
-            a.insts, a.tiles, a.ntiles, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
+        k_step<S, K, false, MODE_STEP, false, QF><<<tile_grid, BLOCK, 0, a.stream>>>(
+            a.insts, a.tiles, a.ntiles, per, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
     } else if (a.split) {
-        k_phi_plane<S, K, QF><<<grid, BLOCK, 0, a.stream>>>(a.insts, a.tiles, a.ntiles, per, fs,
-                                                            rs, ph);
+        k_phi_plane<S, K, QF><<<tile_grid, BLOCK, 0, a.stream>>>(a.insts, a.tiles, a.ntiles, per,
+                                                                 fs, rs, ph);
         if (a.nt_store)
-            k_step<S, K, true, MODE_STEP_NT, true, QF><<<grid, BLOCK, 0, a.stream>>>(
-                a.insts, a.tiles, a.ntiles, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
+            k_step<S, K, true, MODE_STEP_NT, true, QF><<<tile_grid, BLOCK, 0, a.stream>>>(
+                a.insts, a.tiles, a.ntiles, per, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
         else
-            k_step<S, K, true, MODE_STEP, true, QF><<<grid, BLOCK, 0, a.stream>>>(
-                a.insts, a.tiles, a.ntiles, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
+            k_step<S, K, true, MODE_STEP, true, QF><<<tile_grid, BLOCK, 0, a.stream>>>(
+                a.insts, a.tiles, a.ntiles, per, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
+    } else if (stride < per) {
+        // fused step on a persistent grid
+        if (a.nt_store)
+            k_step<S, K, true, MODE_STEP_NT, false, QF, true><<<grid, BLOCK, 0, a.stream>>>(
+                a.insts, a.tiles, a.ntiles, per, stride, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
+        else
+            k_step<S, K, true, MODE_STEP, false, QF, true><<<grid, BLOCK, 0, a.stream>>>(
+                a.insts, a.tiles, a.ntiles, per, stride, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
     } else if (a.nt_store) {
-        k_step<S, K, true, MODE_STEP_NT, false, QF><<<grid, BLOCK, 0, a.stream>>>(
-            a.insts, a.tiles, a.ntiles, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
+        k_step<S, K, true, MODE_STEP_NT, false, QF><<<tile_grid, BLOCK, 0, a.stream>>>(
+            a.insts, a.tiles, a.ntiles, per, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
     } else {
-        k_step<S, K, true, MODE_STEP, false, QF><<<grid, BLOCK, 0, a.stream>>>(
-            a.insts, a.tiles, a.ntiles, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
+        k_step<S, K, true, MODE_STEP, false, QF><<<tile_grid, BLOCK, 0, a.stream>>>(
+            a.insts, a.tiles, a.ntiles, per, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
     }
     return hipGetLastError();
 }
@@ -1123,12 +1151,12 @@ hipError_t moments_s(const StepArgs& a, double* out) {
     const float* rs = (const float*)a.rsrc;
     if (a.pull)
         k_step<S, 1, true, MODE_MOMENTS, false, QF><<<grid, BLOCK, 0, a.stream>>>(
-            a.insts, a.tiles, a.ntiles, per, fs, gs, nullptr, nullptr, (double*)a.q, nullptr,
-            rs, nullptr, out);
+            a.insts, a.tiles, a.ntiles, per, per, fs, gs, nullptr, nullptr, (double*)a.q,
+            nullptr, rs, nullptr, out);
     else
         k_step<S, 1, false, MODE_MOMENTS, false, QF><<<grid, BLOCK, 0, a.stream>>>(
-            a.insts, a.tiles, a.ntiles, per, fs, gs, nullptr, nullptr, (double*)a.q, nullptr,
-            rs, nullptr, out);
+            a.insts, a.tiles, a.ntiles, per, per, fs, gs, nullptr, nullptr, (double*)a.q,
+            nullptr, rs, nullptr, out);
     return hipGetLastError();
 }
 
@@ -1157,7 +1185,43 @@ hipError_t init_q(int qf, const InstDev* insts, int inst, int nx, int ny, const 
     return qf == 5 ? init_s<S, 5>(insts, inst, nx, ny, phi0, ux0, uy0, f, g, q, rplane, st)
                    : init_s<S, 9>(insts, inst, nx, ny, phi0, ux0, uy0, f, g, q, rplane, st);
 }
+// resident blocks per compute unit of the fused pull-step kernel on a persistent grid
+template <typename S, int K, int QF>
+int occ_k(bool nt) {
+    int nb = 0;
+    const hipError_t e =
+        nt ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                 &nb, k_step<S, K, true, MODE_STEP_NT, false, QF, true>, BLOCK, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                 &nb, k_step<S, K, true, MODE_STEP, false, QF, true>, BLOCK, 0);
+    return e == hipSuccess ? nb : 0;
+}
+
+template <typename S, int QF>
+int occ_s(int rows, bool nt) {
+    switch (rows) {
+        case 4: return occ_k<S, 1, QF>(nt);
+        case 8: return occ_k<S, 2, QF>(nt);
+        case 16: return occ_k<S, 4, QF>(nt);
+        default: return 0;
+    }
+}
+
+template <typename S>
+int occ_q(int qf, int rows, bool nt) {
+    return qf == 5 ? occ_s<S, 5>(rows, nt) : occ_s<S, 9>(rows, nt);
+}
+
 }  // namespace
+
+int step_blocks_per_cu(int storage, int qf, int rows, bool nt) {
+    switch (storage) {
+        case STORE_F64: return occ_q<double>(qf, rows, nt);
+        case STORE_F32: return occ_q<float>(qf, rows, nt);
+        case STORE_F16: return occ_q<_Float16>(qf, rows, nt);
+        default: return 0;
+    }
+}
 
 hipError_t launch_step(int storage, const StepArgs& a) {
     if (a.qf != 5 && a.qf != 9) return hipErrorInvalidValue;

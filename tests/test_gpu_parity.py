@@ -215,6 +215,41 @@ def test_variants_bitwise_identical():
             assert np.array_equal(got[k], ref[k]), (kw, k)
 
 
+@pytest.mark.parametrize("storage,qf", [("f64", 9), ("f32", 9), ("f16", 9), ("f32", 5)])
+@pytest.mark.parametrize("rows", [4, 8])
+def test_persistent_grid_bitwise_identical(storage, qf, rows, monkeypatch):
+    """The persistent grid (blocks looping over runs of tiles; here 3 blocks per XCD, so
+    each block takes dozens of tiles across instance boundaries) against one block per
+    tile, on a batch of uneven grids with every boundary type: the same bits."""
+    batch = [cases.droplet_impact(512, 160, D=48, Re=20), cases.spinodal(200, seed=4),
+             cases.layered_poiseuille(20, 72), cases.static_drop(100, 37, R=12)]
+    if qf == 5:
+        for c in batch:
+            c["f_lattice"] = cases.D2Q5
+    out = {}
+    monkeypatch.setenv("LBM_PERSIST_BLOCKS", "3")
+    for grid in ("tiles", "persistent"):
+        with lbm.Simulation(batch, storage=storage, kernel="fused", tile_rows=rows,
+                            stores="cached", grid=grid) as sim:
+            assert sim.info()["grid"] == grid
+            sim.step(41)
+            out[grid] = [sim.moments(k) for k in range(len(batch))]
+    for k in range(len(batch)):
+        for key in out["tiles"][k]:
+            assert np.array_equal(out["tiles"][k][key], out["persistent"][k][key]), (k, key)
+
+
+def test_persistent_grid_full_size_bitwise():
+    """At full size (1024^2, 64 x 4 tiles: 4096 tiles over the resident blocks), with
+    streaming stores and graph replay."""
+    c = cases.spinodal(1024, seed=0)
+    ref = run_hip(c, 20, "f32", kernel="fused", tile_rows=4, stores="streaming", grid="tiles")
+    got = run_hip(c, 20, "f32", kernel="fused", tile_rows=4, stores="streaming",
+                  grid="persistent")
+    for k in ref:
+        assert np.array_equal(got[k], ref[k]), k
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_graph_tiers_bitwise_identical(storage):
     """Replay of 64-, 16- and 2-step graphs plus single launches, with step calls of uneven
@@ -400,25 +435,26 @@ def test_autotune_cache(tmp_path, monkeypatch):
     with the same key takes it from the file; malformed lines are ignored; results are the
     same bits either way."""
     path = tmp_path / "tune.txt"
-    path.write_text("garbage line\nlbm-tune-v1 only-three-fields 1\n")
+    path.write_text("garbage line\nlbm-tune-v2 only-three-fields 1\n")
     monkeypatch.setenv("LBM_AUTOTUNE_CACHE", str(path))
     c = cases.droplet_impact(256, 96, D=40, Re=20)
     with lbm.Simulation(c, storage="f32") as a:
         info_a = a.info()
         a.step(20)
         ref = a.moments()
-    lines = [l for l in path.read_text().splitlines() if l.startswith("lbm-tune-v1 ") and
-             len(l.split()) == 5]
+    lines = [l for l in path.read_text().splitlines() if l.startswith("lbm-tune-v2 ") and
+             len(l.split()) == 6]
     assert len(lines) == 1
-    kern, rows, nt = (int(v) for v in lines[0].split()[2:])
+    kern, rows, nt, pg = (int(v) for v in lines[0].split()[2:])
     assert (kern, rows) == (info_a["kernel"], info_a["tile_rows"])
+    assert (nt, pg) == (info_a["stores"] == "streaming", info_a["grid"] == "persistent")
     with lbm.Simulation(c, storage="f32") as b:
         info_b = b.info()
         b.step(20)
         got = b.moments()
-    assert [l for l in path.read_text().splitlines() if l.startswith("lbm-tune-v1 ") and
-            len(l.split()) == 5] == lines          # found in the cache: nothing appended
-    assert (info_b["kernel"], info_b["tile_rows"], info_b["stores"]) == \
-        (info_a["kernel"], info_a["tile_rows"], info_a["stores"])
+    assert [l for l in path.read_text().splitlines() if l.startswith("lbm-tune-v2 ") and
+            len(l.split()) == 6] == lines          # found in the cache: nothing appended
+    assert (info_b["kernel"], info_b["tile_rows"], info_b["stores"], info_b["grid"]) == \
+        (info_a["kernel"], info_a["tile_rows"], info_a["stores"], info_a["grid"])
     for k in ref:
         assert np.array_equal(ref[k], got[k])
