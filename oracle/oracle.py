@@ -31,11 +31,16 @@ _D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 
 
 def lib():
+    """The oracle library: oracle/liblbm_oracle.so (built on first use), or the build that
+    the environment variable ORACLE_LIB names (the mutation test loads altered copies)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
-            _build.build()
-        L = C.CDLL(_build.LIB)
+        path = os.environ.get("ORACLE_LIB")
+        if not path:
+            path = _build.LIB
+            if not os.path.exists(path):
+                _build.build()
+        L = C.CDLL(path)
         P = C.POINTER(OrcParams)
         L.orc_check.argtypes = [P]
         L.orc_create.argtypes = [P, _D, _D, _D]

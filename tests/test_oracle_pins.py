@@ -4,6 +4,8 @@ None of these compares the oracle with itself: each checks a moment identity of 
 paper's appendix, a closed form, a conservation law, an analytic flow, a symmetry, or an
 independent brute-force reading of the step in 40-digit arithmetic.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -13,6 +15,17 @@ from paper_1710_09541_amd import cases
 
 CS2 = 1.0 / 3.0
 RNG = np.random.default_rng(12345)
+
+
+def paper_value(key):
+    """A number the paper prints, from tests/golden/paper_values.txt (with its citation)."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_values.txt")
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if parts and not parts[0].startswith("#") and parts[0] == key:
+                return float(parts[1])
+    raise KeyError(key)
 
 
 def _lat():
@@ -324,7 +337,7 @@ def test_layered_poiseuille_ratio10_table1():
     s = O.OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
     s.step(20000)
     eu = cases.relative_error_eu(s.moments()["ux"], c["ux_analytic"])
-    assert eu < 3 * 8.9e-3
+    assert eu < 3 * paper_value("poiseuille_Eu_ratio10")
 
 
 def test_layered_poiseuille_single_phase_second_order():
@@ -535,7 +548,8 @@ def test_eq29_static_drop_spurious_velocity_and_laplace():
     s.step(5000)
     m = s.moments()
     umax = float(np.sqrt(m["ux"] ** 2 + m["uy"] ** 2).max())
-    assert 1e-10 < umax < 1e-7
+    u_paper = paper_value("static_drop_max_spurious_velocity")
+    assert u_paper / 16 < umax < u_paper * 64
     c = cases.static_drop(64, 64, R=16.0, W=4.0, sigma=0.01)
     c["grad_scheme"] = cases.GRAD_LOCAL_NEQ
     dp, _ = _dp(c, 3000)
@@ -591,7 +605,7 @@ def test_impact_spreading_power_law():
         assert d["nonfinite"] == 0
         ratios.append(d["spread_radius"] / c["D"] / np.sqrt(t))
     C = float(np.mean(ratios))
-    assert abs(C / 1.35 - 1) < 0.2
+    assert abs(C / paper_value("spreading_prefactor_C") - 1) < 0.2
 
 
 # ------------------------------------------------- D2Q5 phase-field lattice (NEXT f2)
