@@ -447,7 +447,9 @@ void tune_cache_store(const lbm_ctx* c, const std::string& key) {
 // is left untouched.  (The alternation matters: the buffer a step reads was written by the
 // step before, partly still in the last-level cache.)  If the temporary cannot be
 // allocated, the launches repeat from the current buffer into the spare one.  The fastest
-// median of interleaved rounds wins, by a margin of 1 % over smaller tiles.
+// median of interleaved rounds wins, by a margin of 1 % over the candidates listed before
+// it: smaller tiles first, and the store policy expected to win first (streaming stores when
+// a step's working set exceeds the 256 MB last-level cache of MI355X, cached ones below).
 int autotune(lbm_ctx* c) {
     struct Cand {
         int kernel, rows;
@@ -462,11 +464,17 @@ int autotune(lbm_ctx* c) {
     // tile on every workload and format, so timing it at every init is not worth its cost
     const bool want_tiles = c->opt.grid != LBM_GRID_PERSISTENT;
     const bool want_persistent = c->opt.grid == LBM_GRID_PERSISTENT;
+    // bytes one step reads and writes: both buffers of both lattices and the per-node state
+    const double step_bytes = 4.0 * (double)c->dist_elems * c->esize +
+                              (double)c->q_elems * sizeof(double) * 2.0 +
+                              (double)c->mp_elems * sizeof(float) * 2.0;
+    const bool streaming_first = step_bytes > 256.0 * 1024.0 * 1024.0;
     const int rows_opts[3] = {4, 8, 16};
     for (int r : rows_opts) {
         if (c->opt.tile_rows && c->opt.tile_rows != r) continue;
         if (c->storage == STORE_F64 && r == 16) continue;  // 16 rows of doubles spill
-        for (int nt = 0; nt < 2; ++nt) {
+        for (int k = 0; k < 2; ++k) {
+            const int nt = streaming_first ? 1 - k : k;
             if ((nt && !want_nt) || (!nt && !want_cached)) continue;
             for (int pg = 0; pg < 2; ++pg) {
                 if ((pg && !want_persistent) || (!pg && !want_tiles)) continue;
@@ -565,9 +573,9 @@ int autotune(lbm_ctx* c) {
         }
     }
     if (rc == LBM_OK) {
-        // candidates come smallest tile first, cached stores before streaming ones; a later
-        // one must win by more than 1 % (several times the spread of a candidate's timed
-        // rounds), so noise does not flip the choice between near-equal configurations
+        // candidates come smallest tile first, the expected store policy first; a later one
+        // must win by more than 1 % (several times the spread of a candidate's timed rounds),
+        // so noise does not flip the choice between near-equal configurations
         float best = 1e30f;
         for (int ci = 0; ci < nc; ++ci) {
             float* tc = t.data() + (size_t)ci * NREP;
