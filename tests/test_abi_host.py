@@ -86,6 +86,21 @@ def test_invalid_boundary_and_options_rejected():
         assert e.value.code == lbm.LBM_ERR_PARAM
 
 
+@pytest.mark.parametrize("storage,n", [("f64", 7744), ("f32", 10944), ("f16", 15488)])
+def test_instance_beyond_4gib_rejected_before_device(storage, n):
+    """One instance's 9 population planes must stay below 4 GiB (the buffer addressing
+    uses 32-bit byte offsets); the next multiple of 64 above the largest admitted grid is
+    refused before any device call."""
+    c = cases.static_drop(16, 16, R=4)
+    c["nx"] = c["ny"] = n
+    for k in ("phi0", "ux0", "uy0"):
+        c[k] = np.zeros((n, n))
+    with pytest.raises(lbm.LbmError) as e:
+        _init(c, storage=storage)
+    assert e.value.code == lbm.LBM_ERR_PARAM
+    assert "too large" in lbm.lbm_last_error()
+
+
 def test_null_context_calls():
     L = lbm.load()
     assert L.lbm_step(None, 1) == lbm.LBM_ERR_PARAM
