@@ -16,9 +16,10 @@ same device and reported next to it, each with its error against the FP64 CPU or
 
 Also timed: the same spinodal at 4096 x 4096 (working set far above the 256 MB last-level
 cache, so the bandwidth is HBM's), a batch of 256 independent instances of uneven size, the
-spinodal with the D2Q5 phase-field lattice (5 instead of 9 f populations), the static drop
-64 x 64 and the Poiseuille channel 16 x 512 (both so small that launch latency dominates),
-and the droplet impact at 2048 x 512.
+spinodal with the D2Q5 phase-field lattice (5 instead of 9 f populations), with the normal of
+Eq. 29 and with the inverse-linear viscosity of Eq. 25, the static drop 64 x 64 and the
+Poiseuille channel 16 x 512 (both so small that launch latency dominates), and the droplet
+impact at 2048 x 512.
 
 Prints ONE JSON line.  Inputs are resident in device memory before the timed region;
 timing uses HIP events recorded on the stream the library launches on.
@@ -319,6 +320,20 @@ def main():
             log("1024^2 D2Q5 %s: %.1f MLUPS, %.0f GB/s algorithmic" % (st, r["mlups"],
                                                                        r["achieved_gbs"]))
         from paper_1710_09541_amd import cases
+        # the normal of Eq. 29 (local non-equilibrium scheme) instead of the isotropic stencil's
+        q29, _ = workload("spinodal1024")
+        q29[0]["grad_scheme"] = cases.GRAD_LOCAL_NEQ
+        for st in ("f32", "f64", "f16"):
+            r = measure(q29, st, args.steps // 4, args.warmup)
+            extra["spinodal1024_eq29_" + st] = r
+            log("1024^2 Eq. 29 %s: %.1f MLUPS, %.0f GB/s algorithmic" % (st, r["mlups"],
+                                                                         r["achieved_gbs"]))
+        # the inverse-linear viscosity law of Eq. 25
+        qnu, _ = workload("spinodal1024")
+        qnu[0]["visc_law"] = cases.NU_INVERSE
+        r = measure(qnu, "f32", args.steps // 4, args.warmup)
+        extra["spinodal1024_nu_inverse_f32"] = r
+        log("1024^2 Eq. 25 f32: %.1f MLUPS, %.0f GB/s algorithmic" % (r["mlups"], r["achieved_gbs"]))
         small = [("static_drop64_f64", [cases.static_drop()], "f64", 2000),
                  ("poiseuille16x512_f32", [cases.layered_poiseuille()], "f32", 5000),
                  ("impact2048_f32", workload("impact2048")[0], "f32", 2000),
