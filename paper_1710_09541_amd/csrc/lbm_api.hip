@@ -96,6 +96,8 @@ struct lbm_ctx {
     bool persistent = false;   // persistent grid of resident blocks
     int num_cu = 0;            // compute units of the device
     int persist_override = 0;  // LBM_PERSIST_BLOCKS: blocks per XCD of a persistent grid
+    // resident blocks per CU, by tile rows and store policy (-1: not asked yet)
+    mutable int per_cu[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};
     std::string err;
 };
 
@@ -254,7 +256,11 @@ void free_all(lbm_ctx* c) {
 // environment variable LBM_PERSIST_BLOCKS gives
 int persist_blocks(const lbm_ctx* c, int rows, bool nt) {
     if (c->persist_override > 0) return c->persist_override;
-    const int per_cu = step_blocks_per_cu(c->storage, c->qf, rows, nt);
+    const int li = list_index(rows);
+    if (li < 0) return 0;
+    int& cached = c->per_cu[li][nt ? 1 : 0];
+    if (cached < 0) cached = step_blocks_per_cu(c->storage, c->qf, rows, nt);
+    const int per_cu = cached;
     if (per_cu <= 0 || c->num_cu <= 0) return 0;
     return std::max(1, per_cu * c->num_cu / NXCD);
 }
