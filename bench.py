@@ -48,6 +48,8 @@ ESIZE = {"f64": 8, "f32": 4, "f16": 2}
 def alg_bytes(storage, qf=9):
     """Algorithmic bytes per lattice update with a phase-field lattice of qf velocities."""
     return 2 * (qf + 9) * ESIZE[storage] + 32
+
+
 TOL = {"f64": 1e-12, "f32": 1e-5, "f16": 1e-3}
 KERNEL_SRC = os.path.join(ROOT, "paper_1710_09541_amd", "csrc", "lbm_kernels.hip")
 
