@@ -2,12 +2,25 @@
 and measure the max-norm error of each field, normalised as
     E_q = max |q - q_oracle| / max(max |q_oracle|, q_scale)
 with q_scale = 1 for phi, u_scale for u and p_scale for p (set per case)."""
+import os
+
 import numpy as np
 
 from oracle.oracle import OracleSim
 from paper_1710_09541_amd import lbm
 
 TOL = {"f64": 1e-12, "f32": 1e-5, "f16": 1e-3}
+
+
+def paper_value(key):
+    """A number the paper prints, from tests/golden/paper_values.txt (with its citation)."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_values.txt")
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if parts and not parts[0].startswith("#") and parts[0] == key:
+                return float(parts[1])
+    raise KeyError(key)
 
 
 def run_oracle(case, steps):

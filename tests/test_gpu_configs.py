@@ -8,7 +8,7 @@ import pytest
 from oracle import diag
 from oracle.oracle import OracleSim
 from paper_1710_09541_amd import cases, lbm
-from tests.parity import TOL, errors, report, run_oracle, sensitivity
+from tests.parity import TOL, errors, paper_value, report, run_oracle, sensitivity
 
 pytestmark = pytest.mark.gpu
 
@@ -130,13 +130,17 @@ def test_spinodal_1024_20000_steps_reduced_vs_fp64():
 
 
 def test_impact_full_size_spreading_reduced_vs_fp64():
-    """The impact at full size (2048 x 512, D = 256, Re = 100): the spreading radius of FP32
-    and FP16 storage against the FP64 format at t* = 0.5, 1 and 2."""
+    """The impact at full size (2048 x 512, D = 256, Re = 100) to t* = 5 (25,600 steps): the
+    spreading radius of FP32 and FP16 storage against the FP64 format at t* = 0.5 ... 5; and
+    the prefactor C of r/D = C sqrt(t*) (Sec. 3.4), fitted to the FP64 run over t* = 0.5 ... 2
+    (the paper gives no window), within 10 % of the paper's 1.35.  (The FP64 format repeats
+    the oracle's arithmetic bit for bit, so this pins the method at the paper's scale.)"""
     c = cases.droplet_impact(2048, 512, D=256, Re=100)
     T = c["D"] / c["U"]
     sims = {st: lbm.Simulation(c, storage=st) for st in ("f64", "f32", "f16")}
+    ratios = []
     try:
-        for t in (0.5, 1.0, 2.0):
+        for t in (0.5, 1.0, 2.0, 3.0, 4.0, 5.0):
             r = {}
             for st, sim in sims.items():
                 sim.step(int(round(t * T)) - sim.info()["step"])
@@ -147,6 +151,11 @@ def test_impact_full_size_spreading_reduced_vs_fp64():
                   % (t, r["f64"], r["f32"], r["f16"]), flush=True)
             assert abs(r["f32"] / r["f64"] - 1) < 0.01
             assert abs(r["f16"] / r["f64"] - 1) < 0.02
+            ratios.append(r["f64"] / np.sqrt(t))
     finally:
         for sim in sims.values():
             sim.close()
+    C_early = float(np.mean(ratios[:3]))
+    print("[spreading 2048x512] C (FP64) over t* = 0.5-2: %.3f, over 0.5-5: %.3f; r/D / sqrt(t*): %s"
+          % (C_early, float(np.mean(ratios)), " ".join("%.3f" % v for v in ratios)), flush=True)
+    assert abs(C_early / paper_value("spreading_prefactor_C") - 1) < 0.1

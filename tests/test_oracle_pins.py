@@ -4,28 +4,16 @@ None of these compares the oracle with itself: each checks a moment identity of 
 paper's appendix, a closed form, a conservation law, an analytic flow, a symmetry, or an
 independent brute-force reading of the step in 40-digit arithmetic.
 """
-import os
-
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from oracle import diag
 from paper_1710_09541_amd import cases
+from tests.parity import paper_value
 
 CS2 = 1.0 / 3.0
 RNG = np.random.default_rng(12345)
-
-
-def paper_value(key):
-    """A number the paper prints, from tests/golden/paper_values.txt (with its citation)."""
-    path = os.path.join(os.path.dirname(__file__), "golden", "paper_values.txt")
-    with open(path) as fh:
-        for line in fh:
-            parts = line.split()
-            if parts and not parts[0].startswith("#") and parts[0] == key:
-                return float(parts[1])
-    raise KeyError(key)
 
 
 def _lat():
