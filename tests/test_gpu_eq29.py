@@ -91,3 +91,24 @@ def test_eq29_mixed_batch_f64():
         ref = run_oracle(c, 100)
         for key in ref:
             assert np.array_equal(ref[key], got[k][key]), (k, key)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_eq29_paper_static_drop_spurious_velocity(storage):
+    """Sec. 3.1 at the paper's set-up (200 x 200 periodic, R = 50, W = 5, sigma = 1e-3,
+    density ratio 1000, nu = 0.1, M = 0.1, local normal of Eq. 29): the largest spurious
+    speed after 100,000 steps within a factor 2 of the 1.6e-9 the paper prints (it states
+    no step count; measured 1.39e-9 after 1e5 steps and 1.90e-9 after 2e5).  The FP64
+    format repeats the oracle's arithmetic bit for bit, so this pins the method itself over a
+    horizon the oracle cannot afford in a test."""
+    from tests.parity import paper_value
+    c = _neq(cases.static_drop(200, 200, R=50.0, W=5.0, ratio=1000.0, sigma=0.001, nu=0.1,
+                               M=0.1))
+    with lbm.Simulation(c, storage=storage) as sim:
+        sim.step(100000)
+        d = sim.reduce()
+    u_paper = paper_value("static_drop_max_spurious_velocity")
+    print("[spurious] 200x200 drop, Eq. 29, %s, 1e5 steps: max |u| %.3e (paper %.1e)"
+          % (storage, d["max_u"], u_paper), flush=True)
+    assert d["nonfinite"] == 0
+    assert 0.5 < d["max_u"] / u_paper < 2.0
