@@ -145,7 +145,8 @@ def measure(cs, storage, steps, warmup, kernel="auto", tile_rows=0, final_stats=
     ach = alg_bytes(storage, qf) * nodes / per_launch_s / 1e9
     return {"mlups": nodes * steps / (ms / 1e3) / 1e6, "ms_per_step": ms / steps,
             "kernel": info["kernel"], "tile_rows": info["tile_rows"], "stores": info["stores"],
-            "grid": info["grid"],
+            "grid": info["grid"], "tile_order": ("rows" if info["strip"] == "rows"
+                                                 else "strips of %d tiles" % info["strip"]),
             "f_lattice": qf,
             "alg_bytes_per_lu": alg_bytes(storage, qf), "achieved_gbs": ach,
             "frac_hbm_peak": ach / PEAK_HBM_GBS, "nodes": nodes, "steps": steps,
@@ -284,9 +285,9 @@ def main():
     for st in [args.storage] + [v for v in others if v and v != args.storage]:
         r = measure(cs, st, args.steps, args.warmup, args.kernel, args.tile_rows,
                     final_stats=single, stores=args.stores, grid=args.grid)
-        log("%s: %.1f MLUPS, %.4f ms/step, %.0f GB/s algorithmic (%d rows, %s stores, %s grid)"
-            % (st, r["mlups"], r["ms_per_step"], r["achieved_gbs"], r["tile_rows"], r["stores"],
-               r["grid"]))
+        log("%s: %.1f MLUPS, %.4f ms/step, %.0f GB/s algorithmic (%d rows, %s stores, %s grid, "
+            "tile order: %s)" % (st, r["mlups"], r["ms_per_step"], r["achieved_gbs"], r["tile_rows"],
+                                 r["stores"], r["grid"], r["tile_order"]))
         if ref is not None:
             r["accuracy_vs_oracle"] = spinodal_accuracy(cs[0], st, args.cpu_steps + 1, ref)
             log("%s: accuracy %s" % (st, json.dumps(r["accuracy_vs_oracle"])))
@@ -312,7 +313,8 @@ def main():
         for st in ("f32", "f64", "f16"):
             r = measure(big, st, 1000, 20)
             extra["spinodal4096_" + st] = r
-            log("4096^2 %s: %.1f MLUPS, %.0f GB/s algorithmic" % (st, r["mlups"], r["achieved_gbs"]))
+            log("4096^2 %s: %.1f MLUPS, %.0f GB/s algorithmic (%s stores, tile order: %s)"
+                % (st, r["mlups"], r["achieved_gbs"], r["stores"], r["tile_order"]))
         del big
         q5, _ = workload("spinodal1024")
         q5[0]["f_lattice"] = 5
@@ -369,7 +371,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "storage": args.storage, "nodes": nodes,
                    "kernel": kname, "tile_rows": main_r["tile_rows"],
-                   "stores": main_r["stores"], "grid": main_r["grid"]},
+                   "stores": main_r["stores"], "grid": main_r["grid"],
+                   "tile_order": main_r["tile_order"]},
         "roofline": {"bound": "hbm", "achieved": round(main_r["achieved_gbs"], 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(main_r["frac_hbm_peak"], 4),

@@ -91,6 +91,12 @@ enum { LBM_STORES_AUTO = 0, LBM_STORES_CACHED = 1, LBM_STORES_STREAMING = 2 };
  * tiles better than a fixed assignment). */
 enum { LBM_GRID_AUTO = 0, LBM_GRID_TILES = 1, LBM_GRID_PERSISTENT = 2 };
 
+/* Order of the tiles within each instance: whole rows of tiles one after the other, or
+ * vertical strips 8 or 16 tiles (512 or 1024 nodes) wide, row after row inside a strip.
+ * Strips keep the halo rows a tile re-reads in the L2 cache when the grid is much larger
+ * than the caches; whole rows win where it fits.  Results are bitwise identical. */
+enum { LBM_STRIP_AUTO = 0, LBM_STRIP_ROWS = -1 };   /* or a strip width of 8 or 16 tiles */
+
 /* kernel choice for the step */
 enum {
     LBM_KERNEL_AUTO = 0,  /* the autotuner picks */
@@ -136,7 +142,7 @@ typedef struct {
                                  appended to it, keyed by GPU, storage, lattice, options and
                                  grid sizes) */
     int32_t grid;             /* LBM_GRID_* (AUTO: one block per tile) */
-    int32_t reserved;
+    int32_t strip;            /* LBM_STRIP_AUTO (timed at lbm_init), LBM_STRIP_ROWS, 8 or 16 */
 } lbm_options;
 
 /* Integral diagnostics of one instance, FP64 accumulation in a fixed order. */
@@ -194,10 +200,11 @@ int lbm_get_state(lbm_ctx* c, void* buf, size_t* bytes);
 int lbm_set_state(lbm_ctx* c, const void* buf, size_t bytes);
 
 /* Number of steps taken; the kernel (LBM_KERNEL_FUSED / SPLIT), tile rows, population
- * stores (LBM_STORES_CACHED / STREAMING) and launch grid (LBM_GRID_TILES / PERSISTENT) the
- * context runs with.  Any pointer may be NULL; LBM_ERR_PARAM if c is NULL. */
+ * stores (LBM_STORES_CACHED / STREAMING), launch grid (LBM_GRID_TILES / PERSISTENT) and tile
+ * order (LBM_STRIP_ROWS, 8 or 16) the context runs with.  Any pointer may be NULL;
+ * LBM_ERR_PARAM if c is NULL. */
 int lbm_info(const lbm_ctx* c, int64_t* step, int32_t* kernel, int32_t* tile_rows,
-             int32_t* stores, int32_t* grid);
+             int32_t* stores, int32_t* grid, int32_t* strip);
 
 /* Message of the last error of c, or of the calling thread if c is NULL. */
 const char* lbm_last_error(const lbm_ctx* c);

@@ -270,6 +270,35 @@ def test_persistent_grid_full_size_bitwise():
         assert np.array_equal(got[k], ref[k]), k
 
 
+@pytest.mark.parametrize("storage,qf", [("f64", 9), ("f32", 9), ("f16", 9), ("f32", 5)])
+def test_strip_orders_bitwise_identical(storage, qf):
+    """Tiles in vertical strips of 8 or 16 tiles against whole rows, with the fused and the
+    split kernel, on a batch whose widths are above, at and below the strip widths (walls,
+    open side, periodic): the same bits."""
+    batch = [cases.droplet_impact(1300, 96, D=48, Re=20), cases.spinodal(1100, seed=4),
+             cases.layered_poiseuille(20, 72), cases.static_drop(530, 37, R=12)]
+    for c in batch:
+        c["ny"] = min(c["ny"], 96)
+        for k in ("phi0", "ux0", "uy0", "ux_analytic"):
+            if k in c:
+                c[k] = np.ascontiguousarray(c[k][:c["ny"]])
+        if qf == 5:
+            c["f_lattice"] = cases.D2Q5
+    out = {}
+    for strip in ("rows", 8, 16):
+        for kernel in ("fused", "split"):
+            with lbm.Simulation(batch, storage=storage, kernel=kernel, tile_rows=4,
+                                stores="cached", strip=strip) as sim:
+                assert sim.info()["strip"] == strip
+                sim.step(37)
+                out[(strip, kernel)] = [sim.moments(k) for k in range(len(batch))]
+    ref = out[("rows", "fused")]
+    for key, got in out.items():
+        for k in range(len(batch)):
+            for f in ref[k]:
+                assert np.array_equal(got[k][f], ref[k][f]), (key, k, f)
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_graph_tiers_bitwise_identical(storage):
     """Replay of 64-, 16- and 2-step graphs plus single launches, with step calls of uneven
@@ -474,26 +503,27 @@ def test_autotune_cache(tmp_path, monkeypatch):
     with the same key takes it from the file; malformed lines are ignored; results are the
     same bits either way."""
     path = tmp_path / "tune.txt"
-    path.write_text("garbage line\nlbm-tune-v2 only-three-fields 1\n")
+    path.write_text("garbage line\nlbm-tune-v3 only-three-fields 1\n")
     monkeypatch.setenv("LBM_AUTOTUNE_CACHE", str(path))
     c = cases.droplet_impact(256, 96, D=40, Re=20)
     with lbm.Simulation(c, storage="f32") as a:
         info_a = a.info()
         a.step(20)
         ref = a.moments()
-    lines = [l for l in path.read_text().splitlines() if l.startswith("lbm-tune-v2 ") and
-             len(l.split()) == 6]
+    lines = [l for l in path.read_text().splitlines() if l.startswith("lbm-tune-v3 ") and
+             len(l.split()) == 7]
     assert len(lines) == 1
-    kern, rows, nt, pg = (int(v) for v in lines[0].split()[2:])
+    kern, rows, nt, pg, si = (int(v) for v in lines[0].split()[2:])
     assert (kern, rows) == (info_a["kernel"], info_a["tile_rows"])
     assert (nt, pg) == (info_a["stores"] == "streaming", info_a["grid"] == "persistent")
     with lbm.Simulation(c, storage="f32") as b:
         info_b = b.info()
         b.step(20)
         got = b.moments()
-    assert [l for l in path.read_text().splitlines() if l.startswith("lbm-tune-v2 ") and
-            len(l.split()) == 6] == lines          # found in the cache: nothing appended
-    assert (info_b["kernel"], info_b["tile_rows"], info_b["stores"], info_b["grid"]) == \
-        (info_a["kernel"], info_a["tile_rows"], info_a["stores"], info_a["grid"])
+    assert [l for l in path.read_text().splitlines() if l.startswith("lbm-tune-v3 ") and
+            len(l.split()) == 7] == lines          # found in the cache: nothing appended
+    assert (info_b["kernel"], info_b["tile_rows"], info_b["stores"], info_b["grid"],
+            info_b["strip"]) == (info_a["kernel"], info_a["tile_rows"], info_a["stores"],
+                                 info_a["grid"], info_a["strip"])
     for k in ref:
         assert np.array_equal(ref[k], got[k])
