@@ -299,6 +299,24 @@ def test_strip_orders_bitwise_identical(storage, qf):
                 assert np.array_equal(got[k][f], ref[k][f]), (key, k, f)
 
 
+@pytest.mark.parametrize("M", [0.02, 0.1, 0.5])
+def test_mobility_sweep_inverse_viscosity(M):
+    """The mobility sweep with the inverse-linear viscosity of Eq. 25 (static drop, ratio 1000,
+    nu_g = 0.3 != nu_l, tau_phi = 3M + 0.5 from 0.56 to 2.0): the FP64 format bitwise equal to
+    the oracle after 500 steps, FP32 and FP16 storage within their tolerances (FP16 on u)."""
+    c = cases.static_drop(64, 64, R=16.0, W=4.0, sigma=0.01, M=M, visc_law=cases.NU_INVERSE)
+    c["nu_g"] = 0.3
+    ref = run_oracle(c, 500)
+    got = run_hip(c, 500, "f64")
+    for k in ref:
+        assert np.array_equal(got[k], ref[k]), (M, k)
+    for storage, fields in (("f32", ("phi", "u")), ("f16", ("u",))):
+        e = errors(c, run_hip(c, 500, storage), ref)
+        report("mobility sweep M=%g" % M, storage, e)
+        for f in fields:
+            assert e[f] <= TOL[storage], (M, storage, f, e[f])
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_graph_tiers_bitwise_identical(storage):
     """Replay of 64-, 16- and 2-step graphs plus single launches, with step calls of uneven
