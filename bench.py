@@ -14,12 +14,14 @@ same device and reported next to it, each with its error against the FP64 CPU or
 * field by field on the layered Poiseuille channel 16 x 512 after 1000 steps (walls,
   step viscosity, density ratio 1000), where the stated tolerances apply.
 
-Also timed: the same spinodal at 4096 x 4096 (working set far above the 256 MB last-level
-cache, so the bandwidth is HBM's), a batch of 256 independent instances of uneven size, the
-spinodal with the D2Q5 phase-field lattice (5 instead of 9 f populations), with the normal of
-Eq. 29 and with the inverse-linear viscosity of Eq. 25, the static drop 64 x 64 and the
-Poiseuille channel 16 x 512 (both so small that launch latency dominates), and the droplet
-impact at 2048 x 512.
+Also timed:
+* the same spinodal at 4096 x 4096 and a static drop of radius 1024 at 4096 x 4096 (working sets
+  far above the 256 MB last-level cache, so the bandwidth is HBM's);
+* a batch of 256 independent instances of uneven size;
+* the spinodal with the D2Q5 phase-field lattice (5 instead of 9 f populations), with the normal
+  of Eq. 29, and with the inverse-linear viscosity of Eq. 25;
+* the static drop 64 x 64 and the Poiseuille channel 16 x 512 (both so small that launch
+  latency dominates), and the droplet impact at 2048 x 512.
 
 Prints ONE JSON line.  Inputs are resident in device memory before the timed region;
 timing uses HIP events recorded on the stream the library launches on.
@@ -316,6 +318,15 @@ def main():
             log("4096^2 %s: %.1f MLUPS, %.0f GB/s algorithmic (%s stores, tile order: %s)"
                 % (st, r["mlups"], r["achieved_gbs"], r["stores"], r["tile_order"]))
         del big
+        # the static drop at 4096^2 (R = 1024), the pure-HBM point named with the configurations
+        from paper_1710_09541_amd import cases
+        drop = [cases.static_drop(4096, 4096, R=1024.0)]
+        for st in ("f32", "f64", "f16"):
+            r = measure(drop, st, 300, 20)
+            extra["static_drop4096_" + st] = r
+            log("static drop 4096^2 %s: %.1f MLUPS, %.0f GB/s algorithmic (%s stores, tile order: %s)"
+                % (st, r["mlups"], r["achieved_gbs"], r["stores"], r["tile_order"]))
+        del drop
         q5, _ = workload("spinodal1024")
         q5[0]["f_lattice"] = 5
         for st in ("f32", "f64", "f16"):
@@ -323,7 +334,6 @@ def main():
             extra["spinodal1024_d2q5_" + st] = r
             log("1024^2 D2Q5 %s: %.1f MLUPS, %.0f GB/s algorithmic" % (st, r["mlups"],
                                                                        r["achieved_gbs"]))
-        from paper_1710_09541_amd import cases
         # the normal of Eq. 29 (local non-equilibrium scheme) instead of the isotropic stencil's
         q29, _ = workload("spinodal1024")
         q29[0]["grad_scheme"] = cases.GRAD_LOCAL_NEQ
