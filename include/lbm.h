@@ -166,7 +166,7 @@ typedef struct {
  * ux0[k], uy0[k] its initial fields (host, double, [ny][nx]), copied during the call.
  * The initial distributions are the equilibria f = f^eq(phi0, u0) (Eq. 9) and
  * g = g^eq(p = 0, u0) (Eq. 16) with rho = rho(phi0), and phi u of the previous step is
- * phi0 u0.  opt may be NULL (F32 storage, autotuned fused kernel, graphs on).  hip_stream
+ * phi0 u0.  opt may be NULL (F32 storage, every choice autotuned, graphs on).  hip_stream
  * is a hipStream_t the work is ordered on (NULL: the library creates its own).
  * On success *out receives the context. */
 int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
