@@ -159,3 +159,36 @@ def test_impact_full_size_spreading_reduced_vs_fp64():
     print("[spreading 2048x512] C (FP64) over t* = 0.5-2: %.3f, over 0.5-5: %.3f; r/D / sqrt(t*): %s"
           % (C_early, float(np.mean(ratios)), " ".join("%.3f" % v for v in ratios)), flush=True)
     assert abs(C_early / paper_value("spreading_prefactor_C") - 1) < 0.1
+
+
+def test_impact_re500_paper_geometry_reduced_vs_fp64():
+    """Sec. 3.4 at Re = 500 in the paper's own set-up: 1500 x 500, R = 100, film H_w = 0.1 H
+    = 50, so nu_l = DU/Re = 0.02 and nu_g = 10 nu_l.  To t* = 2 (8000 steps), before the
+    splash sheets reach the open top, every format stays finite and FP32 and FP16 storage
+    track the FP64 format (which repeats the oracle's arithmetic bit for bit) in the
+    spreading radius.  Past t* ~ 2.1 the sheets cross the zero-gradient top row and the run
+    loses stability in every format; that range is not asserted here."""
+    c = cases.droplet_impact(1500, 500, D=200, Re=500, film=0.25)
+    assert c["Hw"] == 50.0 and abs(c["nu_l"] - 0.02) < 1e-15
+    with lbm.Simulation(c, storage="f64") as sim:
+        sim.step(100)
+        e = errors(c, sim.moments(), run_oracle(c, 100))
+    report("impact Re500 1500x500 100", "f64", e)
+    assert max(e.values()) <= TOL["f64"]
+    T = c["D"] / c["U"]
+    sims = {st: lbm.Simulation(c, storage=st) for st in ("f64", "f32", "f16")}
+    try:
+        for t in (0.5, 1.0, 1.5, 2.0):
+            r = {}
+            for st, sim in sims.items():
+                sim.step(int(round(t * T)) - sim.info()["step"])
+                d = sim.reduce()
+                assert d["nonfinite"] == 0, (st, t)
+                r[st] = d["spread_radius"] / c["D"]
+            print("[impact Re500 1500x500] t*=%.1f: r/D f64 %.4f f32 %.4f f16 %.4f"
+                  % (t, r["f64"], r["f32"], r["f16"]), flush=True)
+            assert abs(r["f32"] / r["f64"] - 1) < 0.01
+            assert abs(r["f16"] / r["f64"] - 1) < 0.02
+    finally:
+        for sim in sims.values():
+            sim.close()
