@@ -24,7 +24,7 @@ namespace {
 thread_local std::string g_thread_err;
 
 constexpr uint64_t STATE_MAGIC = 0x4c424d5046534154ull;  // "LBMPFSAT"
-constexpr int STATE_VERSION = 3;
+constexpr int STATE_VERSION = 4;
 // steps per captured graph, shortest first: each graph launch costs a few microseconds
 // between the last kernel of one graph and the first of the next, which long graphs spread
 // over more steps (measured: 64 steps per graph 0.6 % faster than 16 at 1024^2 FP32 and 4 %
@@ -59,6 +59,7 @@ struct StateHeader {
     int32_t cur, reserved;
     uint64_t bytes_dist, bytes_q, bytes_mp;
     uint64_t total;
+    uint64_t layout;   // fingerprint of how the bytes are laid out (state_layout)
 };
 
 }  // namespace
@@ -249,6 +250,27 @@ bool strip_differs(const lbm_ctx* c, int strip_tiles) {
     for (const Instance& I : c->inst)
         if (strip_tiles > 0 && strip_tiles * TILE_X < I.p.nx) return true;
     return false;
+}
+
+// FNV-1a over what fixes the meaning of a state's bytes beyond their count: every
+// instance's grid size and FP16 storage scales, and the phase-field lattice.  Two contexts
+// whose instances differ only in their transposes have equal byte counts, for instance.
+uint64_t state_layout(const lbm_ctx* c) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    const auto mix = [&h](const void* p, size_t n) {
+        for (size_t i = 0; i < n; ++i) {
+            h ^= ((const unsigned char*)p)[i];
+            h *= 0x100000001b3ull;
+        }
+    };
+    mix(&c->qf, sizeof c->qf);
+    for (const Instance& I : c->inst) {
+        mix(&I.d.nx, sizeof I.d.nx);
+        mix(&I.d.ny, sizeof I.d.ny);
+        mix(&I.d.scale_f, sizeof I.d.scale_f);
+        mix(&I.d.scale_g, sizeof I.d.scale_g);
+    }
+    return h;
 }
 
 void free_all(lbm_ctx* c) {
@@ -971,6 +993,7 @@ int lbm_get_state(lbm_ctx* c, void* buf, size_t* bytes) {
     h.bytes_q = bq;
     h.bytes_mp = bp;
     h.total = total;
+    h.layout = state_layout(c);
     char* b = (char*)buf;
     memcpy(b, &h, sizeof h);
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -994,6 +1017,9 @@ int lbm_set_state(lbm_ctx* c, const void* buf, size_t bytes) {
     if (h.storage != c->storage || h.n_inst != (int32_t)c->inst.size() || h.bytes_dist != bd ||
         h.bytes_q != bq || h.bytes_mp != bp || h.total != bytes)
         return fail(c, LBM_ERR_PARAM, "state does not match this context");
+    if (h.layout != state_layout(c))
+        return fail(c, LBM_ERR_PARAM,
+                    "state does not match this context (grid sizes, lattice or storage scales)");
     const char* b = (const char*)buf;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(c->f[0], b + sizeof h, bd, hipMemcpyHostToDevice));

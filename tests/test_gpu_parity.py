@@ -423,12 +423,38 @@ def test_checkpoint_of_initial_state():
         assert np.array_equal(ref[k], got[k])
 
 
-def test_state_mismatch_rejected():
-    with lbm.Simulation(cases.static_drop(32, 32, R=8), storage="f32") as a:
+def _d2q5(c):
+    c = dict(c)
+    c["f_lattice"] = 5
+    return c
+
+
+@pytest.mark.parametrize("mine,other,storage", [
+    # another storage format
+    (lambda: cases.static_drop(32, 32, R=8), lambda: cases.static_drop(32, 32, R=8), "f64"),
+    # the transposed grid: the same byte count
+    (lambda: cases.static_drop(64, 128, R=8), lambda: cases.static_drop(128, 64, R=8), "f32"),
+    # another phase-field lattice
+    (lambda: cases.static_drop(32, 32, R=8), lambda: _d2q5(cases.static_drop(32, 32, R=8)), "f32"),
+], ids=["storage", "transposed", "lattice"])
+def test_state_mismatch_rejected(mine, other, storage):
+    a_case = mine()
+    with lbm.Simulation(a_case, storage="f32") as a:
+        a.step(3)
         blob = a.get_state()
-    with lbm.Simulation(cases.static_drop(32, 32, R=8), storage="f64") as b:
+        ref = a.moments()
+    with lbm.Simulation(other(), storage=storage) as b:
+        before = b.moments()
         with pytest.raises(lbm.LbmError):
             b.set_state(blob)
+        # the refused state left the context as it was
+        after = b.moments()
+        assert all(np.array_equal(before[k], after[k]) for k in before)
+    # and the state still restores into a context like the one that wrote it
+    with lbm.Simulation(a_case, storage="f32") as c:
+        c.set_state(blob)
+        got = c.moments()
+    assert all(np.array_equal(ref[k], got[k]) for k in ref)
 
 
 # ------------------------------------------------------------- diagnostics (reductions)
