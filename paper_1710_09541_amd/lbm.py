@@ -146,7 +146,16 @@ def lbm_init(params, options, phi0, ux0, uy0, stream=None):
     L = load()
     n = len(params)
     arr = (lbm_params * n)(*params)
-    keep = [np.ascontiguousarray(a, dtype=np.float64) for a in list(phi0) + list(ux0) + list(uy0)]
+    fields = list(phi0) + list(ux0) + list(uy0)
+    if len(fields) != 3 * n:
+        raise ValueError("need one phi0, ux0 and uy0 per instance")
+    keep = [np.ascontiguousarray(a, dtype=np.float64) for a in fields]
+    for j, a in enumerate(keep):
+        p = params[j % n]
+        # the library reads exactly ny * nx values of each field
+        if a.shape != (p.ny, p.nx):
+            raise ValueError("instance %d: initial field has shape %s, expected (ny, nx) = (%d, %d)"
+                             % (j % n, a.shape, p.ny, p.nx))
     ptrs = [_dptr(a) for a in keep]
     DP = C.POINTER(C.c_double) * n
     h = C.c_void_p()
@@ -175,7 +184,9 @@ def lbm_reduce(ctx, inst, mask=None):
     d = lbm_diag()
     m = None
     if mask is not None:
-        m_arr = np.ascontiguousarray(mask, dtype=np.float64)
+        m_arr = np.ascontiguousarray(mask, dtype=np.float64).ravel()
+        if m_arr.size != 5:
+            raise ValueError("mask is (xc, yc, r_in, r_out, y_row): 5 values")
         m = _dptr(m_arr)
     _check(load().lbm_reduce(ctx, int(inst), m, C.byref(d)), ctx)
     return {k: getattr(d, k) for k, _ in lbm_diag._fields_}

@@ -66,6 +66,9 @@ def _init(case, **kw):
 def test_invalid_parameters_rejected_before_device(key, value):
     c = cases.static_drop(16, 16, R=4)
     c[key] = value
+    if key in ("nx", "ny"):   # fields of the shape the parameters name reach the library
+        for k in ("phi0", "ux0", "uy0"):
+            c[k] = np.zeros((c["ny"], c["nx"]))
     with pytest.raises(lbm.LbmError) as e:
         _init(c)
     assert e.value.code == lbm.LBM_ERR_PARAM
@@ -133,6 +136,25 @@ def test_mixed_phase_field_lattices_rejected():
                      [a["phi0"], b["phi0"]], [a["ux0"], b["ux0"]], [a["uy0"], b["uy0"]])
     assert e.value.code == lbm.LBM_ERR_PARAM
     assert "lattice" in lbm.lbm_last_error()
+
+
+@pytest.mark.parametrize("field", ["phi0", "ux0", "uy0"])
+def test_initial_field_of_wrong_shape_refused(field):
+    """The library reads ny * nx values of each initial field; the binding refuses any other
+    shape (the transpose included) before calling it."""
+    c = cases.static_drop(16, 24, R=4)
+    assert c[field].shape == (24, 16)
+    for bad in (c[field][:-1], c[field].T, c[field].ravel()):
+        d = dict(c)
+        d[field] = bad
+        with pytest.raises(ValueError, match="expected"):
+            lbm.lbm_init([lbm.make_params(d)], lbm.make_options(), [d["phi0"]], [d["ux0"]],
+                         [d["uy0"]])
+
+
+def test_reduce_mask_length_checked():
+    with pytest.raises(ValueError, match="5 values"):
+        lbm.lbm_reduce(None, 0, mask=(0.0, 0.0, 1.0))
 
 
 def test_missing_library_fails_loudly(monkeypatch):
