@@ -196,9 +196,10 @@ int lbm_reduce(lbm_ctx* c, int32_t inst, const double* mask, lbm_diag* out);
 int lbm_get_state(lbm_ctx* c, void* buf, size_t* bytes);
 
 /* Restores a state written by lbm_get_state of a context with the same storage format,
- * phase-field lattice, instance grid sizes and FP16 storage scales; any other state is
- * refused with LBM_ERR_PARAM and the context left as it was.  The physical parameters may
- * differ (a restart may change them).  Synchronises. */
+ * phase-field lattice, instance grid sizes, densities rho_l and rho_g, and FP16 storage
+ * scales; any other state is refused with LBM_ERR_PARAM and the context left as it was.
+ * The other parameters (viscosities, sigma, W, M, body force, boundaries) may differ: a
+ * restart may change them.  Synchronises. */
 int lbm_set_state(lbm_ctx* c, const void* buf, size_t bytes);
 
 /* Number of steps taken; the kernel (LBM_KERNEL_FUSED / SPLIT), tile rows, population

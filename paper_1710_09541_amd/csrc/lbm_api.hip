@@ -253,8 +253,10 @@ bool strip_differs(const lbm_ctx* c, int strip_tiles) {
 }
 
 // FNV-1a over what fixes the meaning of a state's bytes beyond their count: every
-// instance's grid size and FP16 storage scales, and the phase-field lattice.  Two contexts
-// whose instances differ only in their transposes have equal byte counts, for instance.
+// instance's grid size, FP16 storage scales and the two densities (the reduced formats store
+// deviations from equilibria whose g part holds rho(phi)), and the phase-field lattice.
+// Two contexts whose instances differ only in their transposes have equal byte counts,
+// for instance.
 uint64_t state_layout(const lbm_ctx* c) {
     uint64_t h = 0xcbf29ce484222325ull;
     const auto mix = [&h](const void* p, size_t n) {
@@ -269,6 +271,8 @@ uint64_t state_layout(const lbm_ctx* c) {
         mix(&I.d.ny, sizeof I.d.ny);
         mix(&I.d.scale_f, sizeof I.d.scale_f);
         mix(&I.d.scale_g, sizeof I.d.scale_g);
+        mix(&I.d.rho_l, sizeof I.d.rho_l);
+        mix(&I.d.rho_g, sizeof I.d.rho_g);
     }
     return h;
 }
@@ -784,7 +788,7 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
         {&c->rplane[1], c->mp_elems * sizeof(float)},
         {(void**)&c->d_insts, n_inst * sizeof(InstDev)},
         {(void**)&c->mom, 5 * c->max_nodes * sizeof(double)},
-        {(void**)&c->partials, 1024 * 13 * sizeof(double)},
+        {(void**)&c->partials, REDUCE_MAX_BLOCKS * REDUCE_SLOTS * sizeof(double)},
         {(void**)&c->red_out, 16 * sizeof(double)},
     };
     for (auto& a : allocs) {

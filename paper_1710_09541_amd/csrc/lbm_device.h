@@ -14,6 +14,8 @@ enum { STORE_F64 = 0, STORE_F32 = 1, STORE_F16 = 2 };
 constexpr int TILE_X = 64;      // tile width = one wavefront of 64 lanes
 constexpr int BLOCK = 256;      // 4 wavefronts; a tile row group is 4 rows
 constexpr int NXCD = 8;         // MI355X: 8 accelerator complex dies, each with its own L2
+constexpr int REDUCE_SLOTS = 13;        // FP64 partial sums per block of the reductions
+constexpr int REDUCE_MAX_BLOCKS = 1024; // blocks of the partial pass at most
 
 // Per-instance constants, read with uniform (scalar) loads.  Distances are in elements.
 struct InstDev {

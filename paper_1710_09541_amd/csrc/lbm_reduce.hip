@@ -10,7 +10,7 @@ namespace lbm {
 // ------------------------------------------------------------------ reductions
 // Per-block partials over the FP64 moment planes of one instance, then one block folds
 // the partials in a fixed order: the result does not depend on timing.
-constexpr int NRED = 13;
+constexpr int NRED = REDUCE_SLOTS;
 enum {
     R_SPHI, R_SRHO, R_KIN, R_MAXU2, R_MINRHO, R_MINPHI, R_MAXPHI, R_PIN_S, R_PIN_N, R_POUT_S,
     R_POUT_N, R_CROSS, R_NONFIN
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_final(const double* __restrict
 
 int reduce_blocks(int64_t n) {
     int64_t b = (n + BLOCK - 1) / BLOCK;
-    return (int)(b < 1024 ? (b < 1 ? 1 : b) : 1024);
+    return (int)(b < REDUCE_MAX_BLOCKS ? (b < 1 ? 1 : b) : REDUCE_MAX_BLOCKS);
 }
 
 hipError_t launch_reduce(const double* mom, int nx, int ny, int periodic_y, const double* mask,

@@ -436,7 +436,10 @@ def _d2q5(c):
     (lambda: cases.static_drop(64, 128, R=8), lambda: cases.static_drop(128, 64, R=8), "f32"),
     # another phase-field lattice
     (lambda: cases.static_drop(32, 32, R=8), lambda: _d2q5(cases.static_drop(32, 32, R=8)), "f32"),
-], ids=["storage", "transposed", "lattice"])
+    # another density ratio: the stored deviations refer to equilibria built with rho(phi)
+    (lambda: cases.static_drop(32, 32, R=8), lambda: cases.static_drop(32, 32, R=8, ratio=100.0),
+     "f32"),
+], ids=["storage", "transposed", "lattice", "densities"])
 def test_state_mismatch_rejected(mine, other, storage):
     a_case = mine()
     with lbm.Simulation(a_case, storage="f32") as a:
