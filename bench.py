@@ -155,6 +155,34 @@ def measure(cs, storage, steps, warmup, kernel="auto", tile_rows=0, final_stats=
             **({"end_of_run": stats} if stats else {})}
 
 
+def host_round_trip(cs, storage, steps, r):
+    """The whole job as a host caller sees it: lbm_init from host fields (device buffers,
+    the FP64 upload of phi0, ux0, uy0, the initial equilibria), `steps` steps, and
+    lbm_moments back to host memory (five FP64 planes), timed on the host clock.  The launch
+    configuration is the one the timed run used, given explicitly, so no autotuning runs."""
+    import torch
+    from paper_1710_09541_amd import lbm
+    nodes = sum(c["nx"] * c["ny"] for c in cs)
+    strip = "rows" if r["tile_order"] == "rows" else int(r["tile_order"].split()[2])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim = lbm.Simulation(cs, storage=storage, kernel=r["kernel"], tile_rows=r["tile_rows"],
+                         stores=r["stores"], grid=r["grid"], strip=strip)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for k in range(len(cs)):
+        sim.moments(k)
+    t3 = time.perf_counter()
+    sim.close()
+    return {"steps": steps, "init_ms": (t1 - t0) * 1e3, "steps_ms": (t2 - t1) * 1e3,
+            "moments_ms": (t3 - t2) * 1e3, "upload_bytes": 3 * 8 * nodes,
+            "download_bytes": 5 * 8 * nodes,
+            "mlups": nodes * steps / (t3 - t0) / 1e6}
+
+
 def crossings_length(phi):
     n = phi.size
     s = phi >= 0.5
@@ -365,6 +393,11 @@ def main():
                 % (st, r["mlups"], r["nodes"], r["achieved_gbs"]))
 
     main_r = results[args.storage]
+    # host to host: not the measured value (inputs are resident in HBM there), reported beside it
+    trip = [host_round_trip(cs, args.storage, n, main_r) for n in (1, args.steps)]
+    for t in trip:
+        log("host round trip, %d steps: init %.1f ms, steps %.1f ms, moments %.1f ms: %.1f MLUPS"
+            % (t["steps"], t["init_ms"], t["steps_ms"], t["moments_ms"], t["mlups"]))
     kname = {1: "k_step (fused)", 2: "k_phi_plane + k_step (split)"}[main_r["kernel"]]
     out = {
         "metric": METRIC,
@@ -390,6 +423,7 @@ def main():
                      "kernel": kname,
                      "alg_bytes_per_launch": ALG_BYTES[args.storage] * nodes},
         "cpu_baseline": base,
+        "host_round_trip": trip,
         "variants": results,
         "extra": extra,
         "kernel_source_sha256": kernel_source_hash(),
