@@ -524,6 +524,32 @@ def test_moments_device_matches_host():
         assert np.array_equal(dev[i], host[k])
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_caller_stream(storage):
+    """A context on a caller's torch stream: the same bits as on the library's own stream,
+    and work the caller queues on that stream after lbm_step / lbm_moments_device sees their
+    results with no synchronisation in between."""
+    import torch
+    c = cases.droplet_impact(256, 96, D=40, Re=20)
+    nx, ny = c["nx"], c["ny"]
+    with lbm.Simulation(c, storage=storage) as a:
+        a.step(120)
+        ref = a.moments()
+    s = torch.cuda.Stream()
+    buf = torch.empty(5 * nx * ny, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    with lbm.Simulation(c, storage=storage, stream=s.cuda_stream) as b:
+        b.step(120)
+        lbm.lbm_moments_device(b.ctx, 0, buf.data_ptr())
+        with torch.cuda.stream(s):
+            out = buf * 1.0          # ordered after the library's work on s
+        s.synchronize()
+        assert b.info()["step"] == 120
+    dev = out.cpu().numpy().reshape(5, ny, nx)
+    for i, k in enumerate(("phi", "rho", "p", "ux", "uy")):
+        assert np.array_equal(dev[i], ref[k]), k
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 def test_streaming_stores_bitwise(storage):
     """Non-temporal population stores (fused and split kernels) give the same bits as
