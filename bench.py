@@ -40,15 +40,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (both lattices) and % HBM roofline, FP32/FP16 vs FP64 at stated error"
 PEAK_HBM_GBS = 8000.0
-# algorithmic bytes per lattice update of the fused step: 9 f + 9 g populations read and
-# written once, plus the per-node state beside them read and written once: FP64 phi u of
-# the previous step (2 doubles); reduced formats the FP32 planes phi_w, p_w, ux_w, uy_w
-ALG_BYTES = {"f64": 36 * 8 + 4 * 8, "f32": 36 * 4 + 8 * 4, "f16": 36 * 2 + 8 * 4}
 ESIZE = {"f64": 8, "f32": 4, "f16": 2}
 
 
 def alg_bytes(storage, qf=9):
-    """Algorithmic bytes per lattice update with a phase-field lattice of qf velocities."""
+    """Algorithmic bytes per lattice update of the fused step with a phase-field lattice of
+    qf velocities: qf f and 9 g populations read and written once, plus the per-node state
+    beside them read and written once (32 bytes: FP64 phi u of the previous step, 2 doubles;
+    the reduced formats' FP32 planes phi_w, p_w, ux_w, uy_w).  D2Q9: FP64 320, FP32 176,
+    FP16 104."""
     return 2 * (qf + 9) * ESIZE[storage] + 32
 
 
@@ -82,6 +82,18 @@ def workload(name):
         desc = ("spinodal decomposition 1024x1024 periodic, phi0=0.5+U[-0.01,0.01] seed 0, "
                 "rho_l/rho_g=3, sigma=1e-3, W=4, M=0.1, nu_l=0.1, nu_g=1.0")
         return [c], desc
+    if name in ("spinodal1024_d2q5", "spinodal1024_eq29", "spinodal1024_nu_inverse"):
+        c = cases.spinodal(1024, seed=0)
+        if name.endswith("d2q5"):        # the D2Q5 phase-field lattice
+            c["f_lattice"] = 5
+            what = "D2Q5 phase-field lattice"
+        elif name.endswith("eq29"):      # the normal of Eq. 29 (local non-equilibrium scheme)
+            c["grad_scheme"] = cases.GRAD_LOCAL_NEQ
+            what = "normal from Eq. 29"
+        else:                            # the inverse-linear viscosity law of Eq. 25
+            c["visc_law"] = cases.NU_INVERSE
+            what = "viscosity law of Eq. 25"
+        return [c], "spinodal decomposition 1024x1024 as spinodal1024, %s" % what
     if name == "spinodal4096":
         c = cases.spinodal(4096, seed=0)
         return [c], "spinodal decomposition 4096x4096 periodic, as spinodal1024 otherwise"
@@ -272,6 +284,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 4096^2 and 256-instance batch measurements")
+    ap.add_argument("--no-round-trip", action="store_true",
+                    help="skip the host-to-host job timing (profiled runs: the step kernel's last "
+                         "dispatches are then the timed ones)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -355,24 +370,21 @@ def main():
             log("static drop 4096^2 %s: %.1f MLUPS, %.0f GB/s algorithmic (%s stores, tile order: %s)"
                 % (st, r["mlups"], r["achieved_gbs"], r["stores"], r["tile_order"]))
         del drop
-        q5, _ = workload("spinodal1024")
-        q5[0]["f_lattice"] = 5
+        q5, _ = workload("spinodal1024_d2q5")
         for st in ("f32", "f64", "f16"):
             r = measure(q5, st, args.steps // 4, args.warmup)
             extra["spinodal1024_d2q5_" + st] = r
             log("1024^2 D2Q5 %s: %.1f MLUPS, %.0f GB/s algorithmic" % (st, r["mlups"],
                                                                        r["achieved_gbs"]))
         # the normal of Eq. 29 (local non-equilibrium scheme) instead of the isotropic stencil's
-        q29, _ = workload("spinodal1024")
-        q29[0]["grad_scheme"] = cases.GRAD_LOCAL_NEQ
+        q29, _ = workload("spinodal1024_eq29")
         for st in ("f32", "f64", "f16"):
             r = measure(q29, st, args.steps // 4, args.warmup)
             extra["spinodal1024_eq29_" + st] = r
             log("1024^2 Eq. 29 %s: %.1f MLUPS, %.0f GB/s algorithmic" % (st, r["mlups"],
                                                                          r["achieved_gbs"]))
         # the inverse-linear viscosity law of Eq. 25
-        qnu, _ = workload("spinodal1024")
-        qnu[0]["visc_law"] = cases.NU_INVERSE
+        qnu, _ = workload("spinodal1024_nu_inverse")
         r = measure(qnu, "f32", args.steps // 4, args.warmup)
         extra["spinodal1024_nu_inverse_f32"] = r
         log("1024^2 Eq. 25 f32: %.1f MLUPS, %.0f GB/s algorithmic" % (r["mlups"], r["achieved_gbs"]))
@@ -394,7 +406,8 @@ def main():
 
     main_r = results[args.storage]
     # host to host: not the measured value (inputs are resident in HBM there), reported beside it
-    trip = [host_round_trip(cs, args.storage, n, main_r) for n in (1, args.steps)]
+    trip = ([] if args.no_round_trip else
+            [host_round_trip(cs, args.storage, n, main_r) for n in (1, args.steps)])
     for t in trip:
         log("host round trip, %d steps: init %.1f ms, steps %.1f ms, moments %.1f ms: %.1f MLUPS"
             % (t["steps"], t["init_ms"], t["steps_ms"], t["moments_ms"], t["mlups"]))
@@ -421,7 +434,7 @@ def main():
                      "frac": round(main_r["frac_hbm_peak"], 4),
                      "traffic": traffic_from_profile(args.workload, args.storage),
                      "kernel": kname,
-                     "alg_bytes_per_launch": ALG_BYTES[args.storage] * nodes},
+                     "alg_bytes_per_launch": main_r["alg_bytes_per_lu"] * nodes},
         "cpu_baseline": base,
         "host_round_trip": trip,
         "variants": results,
