@@ -279,17 +279,28 @@ __device__ __forceinline__ void pull_local(const InstDev& I, int gy, int lx, int
 //   phi = base + sum_i w_i (ref_i - base) + 2^-exp_f sum_i v_i           (Eq. 12)
 // For the rest-deviation formats *res receives the rounding error of the final addition
 // (exact, by Knuth's two-sum): phi + res is the sum before rounding to the phi format.
-template <typename C, bool REF, int QF>
+// SCALED (16-bit storage): the scaled sum is formed with one fused multiply-add per value,
+// which reads the 16-bit value directly; 2^-exp_f is a power of two, so every product is
+// exact and the partial sums round exactly as those of the unscaled values.
+template <typename C, bool REF, int QF, bool SCALED = false>
 __device__ __forceinline__ C phi_of(const C (&v)[9], const C (&ref)[9], C base, C isf,
                                     C* res = nullptr) {
-    C s = v[0];
+    C s;
+    if constexpr (SCALED) {
+        s = __builtin_fmaf(v[0], isf, 0.0f);
 #pragma unroll
-    for (int i = 1; i < QF; ++i) s += v[i];
-    if (!REF) return s * isf;
+        for (int i = 1; i < QF; ++i) s = __builtin_fmaf(v[i], isf, s);
+    } else {
+        s = v[0];
+#pragma unroll
+        for (int i = 1; i < QF; ++i) s += v[i];
+        s = s * isf;
+    }
+    if (!REF) return s;
     C a = wf<C, QF>(0) * (ref[0] - base);
 #pragma unroll
     for (int i = 1; i < QF; ++i) a += wf<C, QF>(i) * (ref[i] - base);
-    const C d = a + s * isf;
+    const C d = a + s;
     const C phi = base + d;
     if (res) {
         const C bv = phi - base;
@@ -684,6 +695,12 @@ __device__ __forceinline__ void step_tile(
     using C = typename Store<S>::C;
     constexpr bool REF = rest_deviation<S>();
     constexpr bool SCALED = sizeof(S) < sizeof(float);   // only the 16-bit format is scaled
+    // a stored 16-bit value times 2^-exp as one fused multiply-add that reads it directly
+    // (the product is exact; with no scale the value is used as it is)
+    const auto unscale = [](C v, C is) -> C {
+        if constexpr (SCALED) return __builtin_fmaf(v, is, 0.0f);
+        else return v;
+    };
     constexpr int TY = 4 * K;
     constexpr int LW = TILE_X + 2;
     constexpr int NR = REF ? (TY + 4) * RW : 1;
@@ -833,7 +850,7 @@ __device__ __forceinline__ void step_tile(
                 for (int i = 0; i < QF; ++i) ref[i] = sw[r[i]].x;
                 base = sw[(yl + 2) * RW + lx + 2].x;
             }
-            sphi[(yl + 1) * LW + lx + 1] = phi_of<C, REF, QF>(f[k], ref, base, isf, &res[k]);
+            sphi[(yl + 1) * LW + lx + 1] = phi_of<C, REF, QF, SCALED>(f[k], ref, base, isf, &res[k]);
         }
     }
     if (on_ring) {
@@ -853,7 +870,7 @@ __device__ __forceinline__ void step_tile(
                 for (int i = 0; i < QF; ++i) ref[i] = sw[r[i]].x;
                 base = sw[(lyl + 2) * RW + rx + 2].x;
             }
-            v = phi_of<C, REF, QF>(rfv, ref, base, isf);
+            v = phi_of<C, REF, QF, SCALED>(rfv, ref, base, isf);
         }
         sphi[(ry + 1) * LW + rx + 1] = v;
     }
@@ -882,8 +899,8 @@ __device__ __forceinline__ void step_tile(
             for (int i = 0; i < 9; ++i) {
                 const float4 q4 = sq[r[i]];
                 const float2 q2 = sw[r[i]];
-                if (i < QF) fd[i] = __builtin_fmaf(wf<float, QF>(i), q2.x - phi, f[k][i] * isf);
-                eg[i] = g[k][i] * isg;
+                if (i < QF) fd[i] = __builtin_fmaf(wf<float, QF>(i), q2.x - phi, unscale(f[k][i], isf));
+                eg[i] = unscale(g[k][i], isg);
                 gs[i] = geq_ref(dir[i], q4.x, q4.y, q4.z, q4.w, q2.y);
             }
             const int me = (yl + 2) * RW + lx + 2;
@@ -1008,7 +1025,8 @@ __global__ __launch_bounds__(BLOCK) void k_phi_plane(
                 for (int i = 0; i < QF; ++i) ref[i] = rb[src[i]].x;
                 base = rb[y * I.pitch + x].x;
             }
-            phiplane[I.off_phi + y * I.pitch + x] = phi_of<C, REF, QF>(v, ref, base, isf);
+            phiplane[I.off_phi + y * I.pitch + x] =
+                phi_of<C, REF, QF, (sizeof(S) < sizeof(float))>(v, ref, base, isf);
         }
     }
 }
