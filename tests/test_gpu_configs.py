@@ -192,3 +192,37 @@ def test_impact_re500_paper_geometry_reduced_vs_fp64():
     finally:
         for sim in sims.values():
             sim.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_batch256_full_size_sampled_instances(storage):
+    """The benchmarked batch as timed: 256 static-drop / layered-channel instances, 32..512
+    per axis (1.9e7 nodes, seed 1), one context, autotuned launch, 100 steps.  Eight of the
+    instances (the smallest, the largest, the widest, the tallest and four drawn with a
+    fixed seed) against the oracle run of that instance alone: FP64 bitwise, FP32 to the
+    storage tolerance (phi: or 4x the oracle's own spread, for a drop centred on a node)."""
+    batch = cases.batch_ensemble(256, seed=1)
+    nodes = [c["nx"] * c["ny"] for c in batch]
+    pick = {int(np.argmin(nodes)), int(np.argmax(nodes)),
+            int(np.argmax([c["nx"] for c in batch])), int(np.argmax([c["ny"] for c in batch]))}
+    rng = np.random.default_rng(7)
+    while len(pick) < 8:
+        pick.add(int(rng.integers(len(batch))))
+    steps = 100
+    with lbm.Simulation(batch, storage=storage) as sim:
+        sim.step(steps)
+        got = {k: sim.moments(k) for k in sorted(pick)}
+        info = sim.info()
+    print("[batch256 %s] %d nodes, launch %s" % (storage, sum(nodes), info), flush=True)
+    for k in sorted(pick):
+        c = batch[k]
+        e = errors(c, got[k], run_oracle(c, steps))
+        report("batch256 inst %d %dx%d %s" % (k, c["nx"], c["ny"], c["name"]), storage, e)
+        if storage == "f64":
+            assert max(e.values()) <= TOL["f64"]
+            continue
+        assert e["u"] <= TOL["f32"]
+        bound = TOL["f32"]
+        if e["phi"] > bound:
+            bound = max(bound, 4.0 * sensitivity(c, steps)["phi"])
+        assert e["phi"] <= bound
