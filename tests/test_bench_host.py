@@ -55,6 +55,11 @@ def test_committed_profiles_name_their_commands_and_kernel():
         if name.startswith("step_"):
             text = open(path).read()
             assert "rocprofv3" in text and "Kernel code hash" in text, name
+            # the summary averages the step kernel's last `steps` dispatches, which are the
+            # timed ones only when the traced bench command skips the host round trip
+            traced = [l for l in text.splitlines() if "--kernel-trace" in l and "bench.py" in l
+                      and "--calibrate-copy" not in l]
+            assert traced and all("--no-round-trip" in l for l in traced), name
         if name.startswith("pmc_"):
             d = json.load(open(path))
             assert {"kernel", "kernel_source_sha256", "avg_duration_ns",
