@@ -226,3 +226,36 @@ def test_batch256_full_size_sampled_instances(storage):
         if e["phi"] > bound:
             bound = max(bound, 4.0 * sensitivity(c, steps)["phi"])
         assert e["phi"] <= bound
+
+
+def test_impact_re500_wall_top_stays_finite():
+    """The same Re = 500 set-up (1500 x 500, R = 100, H_w = 50) with a bounce-back wall in
+    place of the open top: the bulk update stays finite to t* = 4 (16,000 steps) in every
+    format, sum(phi) holds to round-off, and the FP32 and FP16 spreading radii track the
+    FP64 format's.  With the open top the run fails once the splash reaches that side
+    (t* ~ 2.1-2.4); the wall isolates that failure to the open-side rule."""
+    c = cases.droplet_impact(1500, 500, D=200, Re=500, film=0.25)
+    c["bc_yhi"] = cases.WALL
+    T = c["D"] / c["U"]
+    sims = {st: lbm.Simulation(c, storage=st) for st in ("f64", "f32", "f16")}
+    try:
+        s0 = {st: sim.reduce()["sum_phi"] for st, sim in sims.items()}
+        for t in (1.0, 2.0, 3.0, 4.0):
+            r = {}
+            for st, sim in sims.items():
+                sim.step(int(round(t * T)) - sim.info()["step"])
+                d = sim.reduce()
+                assert d["nonfinite"] == 0, (st, t)
+                r[st] = d["spread_radius"] / c["D"]
+                drift = abs(d["sum_phi"] - s0[st]) / s0[st]
+                # FP64: round-off only, the bound of the oracle's conservation pin (20 ulp a step)
+                bound = {"f64": 20 * np.finfo(float).eps * sim.info()["step"], "f32": 1e-6,
+                         "f16": 1e-4}[st]
+                assert drift < bound, (st, t, drift)
+            print("[impact Re500 wall top] t*=%.1f: r/D f64 %.4f f32 %.4f f16 %.4f"
+                  % (t, r["f64"], r["f32"], r["f16"]), flush=True)
+            assert abs(r["f32"] / r["f64"] - 1) < 0.01
+            assert abs(r["f16"] / r["f64"] - 1) < 0.02
+    finally:
+        for sim in sims.values():
+            sim.close()
