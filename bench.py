@@ -1,23 +1,29 @@
 """Benchmark of the phase-field lattice Boltzmann step on one MI355X.
 
 One step = one time step of both D2Q9 lattices (phase field f and flow g) over the whole
-workload.  The default workload is the spinodal-decomposition case: 1024 x 1024 periodic,
-phi0 = 0.5 + U[-0.01, 0.01] (seed 0), rho_l / rho_g = 3, sigma = 1e-3, W = 4, M = 0.1,
-nu_l = 0.1, nu_g = 1.0.  The headline value is MLUPS (million lattice-node updates of both
-lattices per second) with FP32 storage; FP64 and FP16-deviation storage are timed on the
-same device and reported next to it, each with its error against the FP64 CPU oracle:
+workload.  The default workload is the largest single-GPU configuration: a batch of 256
+independent static-drop / layered-Poiseuille instances of uneven size (grids uniform in
+32..512 per axis, density ratio 10/100/1000, seed 1; 19,195,714 nodes), advanced together
+in one launch per step.  The headline value is MLUPS (million lattice-node updates of both
+lattices per second) with FP32 storage; the FP64 format is timed on the same device and
+reported next to it.  Each format states its error against the FP64 CPU oracle:
 
-* on the benchmarked workload, over the oracle's timed sample: the coarsening length
-  L = 2 N / (phase-boundary crossings) and the drift of sum(phi) (the spinodal is chaotic,
-  so fields agree only statistically beyond a few steps; the FP64 format repeats the
-  oracle's arithmetic and its field error is reported as well);
+* per instance, on a sample of the batch (every 16th instance) after the oracle's timed
+  steps, max-norm errors of phi, u and p against the oracle run of each instance alone;
 * field by field on the layered Poiseuille channel 16 x 512 after 1000 steps (walls,
   step viscosity, density ratio 1000), where the stated tolerances apply.
 
-Also timed:
+The roofline fraction counts the algorithmic bytes of the method: every population read
+and written once, phi written and read once and phi u of the previous step read and
+written once (168 B per lattice update in FP32, 336 in FP64, 96 with 16-bit
+populations).  The kernel's own design moves a 16-byte per-node state each way instead of
+the phi plane and phi u (176 / 320 / 104 B); that figure is reported beside it.
+
+Also timed (unless --no-extra):
+* the spinodal decomposition 1024 x 1024 (the earlier headline; phi0 = 0.5 + U[-0.01, 0.01],
+  ratio 3) in all three formats, with the oracle's coarsening length beside it;
 * the same spinodal at 4096 x 4096 and a static drop of radius 1024 at 4096 x 4096 (working sets
   far above the 256 MB last-level cache, so the bandwidth is HBM's);
-* a batch of 256 independent instances of uneven size;
 * the spinodal with the D2Q5 phase-field lattice (5 instead of 9 f populations), with the normal
   of Eq. 29, and with the inverse-linear viscosity of Eq. 25;
 * the static drop 64 x 64 and the Poiseuille channel 16 x 512 (both so small that launch
@@ -44,12 +50,22 @@ ESIZE = {"f64": 8, "f32": 4, "f16": 2}
 
 
 def alg_bytes(storage, qf=9):
-    """Algorithmic bytes per lattice update of the fused step with a phase-field lattice of
-    qf velocities: qf f and 9 g populations read and written once, plus the per-node state
-    beside them read and written once (32 bytes: FP64 phi u of the previous step, 2 doubles;
-    the reduced formats' FP32 planes phi_w, p_w, ux_w, uy_w).  D2Q9: FP64 320, FP32 176,
-    FP16 104."""
+    """Bytes per lattice update that the fused step kernel moves by design, with a
+    phase-field lattice of qf velocities: qf f and 9 g populations read and written once,
+    plus the per-node state beside them read and written once (32 bytes: FP64 phi u of the
+    previous step, 2 doubles; the reduced formats' FP32 planes phi_w, p_w, ux_w, uy_w).
+    D2Q9: FP64 320, FP32 176, FP16 104."""
     return 2 * (qf + 9) * ESIZE[storage] + 32
+
+
+def method_bytes(storage, qf=9):
+    """Algorithmic bytes per lattice update that the method itself must move: qf f and 9 g
+    populations read and written once, phi written and read once and phi u of the previous
+    step (two values) read and written once, all in the storage's word for the populations
+    and its compute word for phi and phi u (FP64: 8 bytes; otherwise 4).  D2Q9: FP64 336,
+    FP32 168, FP16 96 (phi and phi u in FP32)."""
+    aux = 8 if storage == "f64" else 4
+    return 2 * (qf + 9) * ESIZE[storage] + 6 * aux
 
 
 TOL = {"f64": 1e-12, "f32": 1e-5, "f16": 1e-3}
@@ -245,6 +261,91 @@ def host_cpu():
     return "unknown"
 
 
+def host_threads():
+    """Threads the oracle's OpenMP loops use by default on this host."""
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
+
+
+def set_oracle_threads(n):
+    """Sets the OpenMP thread count of the calling thread's later parallel regions (the
+    oracle's loops) through the OpenMP runtime the oracle is linked with."""
+    import ctypes
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
+def batch_cpu_baseline(cs, steps, every=16):
+    """The FP64 oracle timed on this host's cores over a bounded sample of the batch: with
+    all threads on every instance, and with one thread on every `every`-th instance.  Each
+    instance is created, stepped once untimed and then `steps` timed steps; only the timed
+    steps count.  Returns the baseline record and the oracle's moments of the sampled
+    instances after 1 + steps steps, keyed by instance index."""
+    from oracle.oracle import OracleSim
+    threads = host_threads()
+    runs = {}
+
+    def run(idx, nthreads, keep):
+        set_oracle_threads(nthreads)
+        lu, secs = 0, 0.0
+        for k in idx:
+            c = cs[k]
+            s = OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
+            s.step(1)
+            t0 = time.perf_counter()
+            s.step(steps)
+            secs += time.perf_counter() - t0
+            lu += c["nx"] * c["ny"] * steps
+            if keep:
+                runs[k] = s.moments()
+            del s
+        return lu / secs / 1e6, secs, lu
+
+    sample = list(range(0, len(cs), every))
+    all_mlups, all_s, all_lu = run(range(len(cs)), threads, False)
+    one_mlups, one_s, one_lu = run(sample, 1, True)
+    set_oracle_threads(threads)
+    return {"value": all_mlups, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "host": host_cpu(),
+            "value_1_thread": one_mlups, "cores_1_thread": 1,
+            "sample": ("batch of %d instances, FP64, %d steps each after 1 untimed step: all "
+                       "instances on %d threads (%.2e lattice updates, %.1f s); every %dth "
+                       "instance (%d) on 1 thread (%.2e lattice updates, %.1f s)"
+                       % (len(cs), steps, threads, all_lu, all_s, every, len(sample), one_lu,
+                          one_s))}, runs
+
+
+def batch_accuracy(cs, storage, steps, refs, r):
+    """Per-instance max-norm errors (phi, u, p) of the batched GPU run after `steps` steps
+    against the oracle run of each sampled instance alone, in the launch configuration `r`
+    of the timed run (no autotuning).  For a drop whose centre falls on a node, where the
+    normal's direction is set by rounding, phi and p are also given outside a disc around
+    that node fixed before the run (tests/parity.centre_node_mask); the tolerance is judged
+    there, and on u everywhere."""
+    from paper_1710_09541_amd import lbm
+    from tests.parity import centre_node_mask, errors, errors_outside
+    strip = "rows" if r["tile_order"] == "rows" else int(r["tile_order"].split()[2])
+    worst = {"phi": 0.0, "u": 0.0, "p": 0.0}
+    judged = {"phi": 0.0, "u": 0.0, "p": 0.0}
+    with lbm.Simulation(cs, storage=storage, kernel=r["kernel"], tile_rows=r["tile_rows"],
+                        stores=r["stores"], grid=r["grid"], strip=strip) as sim:
+        sim.step(steps)
+        for k, ref in refs.items():
+            got = sim.moments(k)
+            e = errors(cs[k], got, ref)
+            mask = centre_node_mask(cs[k], steps)
+            o = e if mask is None else errors_outside(cs[k], got, ref, mask)
+            for q in worst:
+                worst[q] = max(worst[q], float(e[q]))
+                judged[q] = max(judged[q], float(e[q] if q == "u" else o[q]))
+    tol = TOL[storage]
+    ok = judged["u"] <= tol and (storage == "f16" or judged["phi"] <= tol)
+    return {"steps": steps, "instances": sorted(refs), "max_err": worst,
+            "max_err_outside_centre_nodes": judged, "tol": tol, "within_tol": bool(ok)}
+
+
 def cpu_baseline(c, steps):
     """The FP64 oracle timed on this host's cores over a bounded sample of the workload."""
     from oracle.oracle import OracleSim
@@ -270,20 +371,24 @@ def cpu_baseline(c, steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="spinodal1024")
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="batch256")
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--kernel", default="auto")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--stores", default="auto", choices=["auto", "cached", "streaming"])
     ap.add_argument("--grid", default="auto", choices=["auto", "tiles", "persistent"])
-    ap.add_argument("--variants", default="f64,f16", help="other storages to time ('none' for none)")
-    ap.add_argument("--cpu-steps", type=int, default=1500,
-                    help="oracle steps of the CPU baseline (also the accuracy horizon)")
+    ap.add_argument("--variants", default=None,
+                    help="other storages to time, comma-separated ('none' for none; default "
+                         "f64 for the batch, f64,f16 otherwise)")
+    ap.add_argument("--cpu-steps", type=int, default=None,
+                    help="oracle steps of the CPU baseline, also the accuracy horizon (default "
+                         "40 for the batch, 1500 for a single spinodal)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the 4096^2 and 256-instance batch measurements")
+                    help="skip the other workloads (spinodal 1024^2 and 4096^2, static drop "
+                         "4096^2, rows f1-f3, small grids, impact)")
     ap.add_argument("--no-round-trip", action="store_true",
                     help="skip the host-to-host job timing (profiled runs: the step kernel's last "
                          "dispatches are then the timed ones)")
@@ -315,18 +420,27 @@ def main():
 
     cs, desc = workload(args.workload)
     nodes = sum(c["nx"] * c["ny"] for c in cs)
-    log("workload %s, %d nodes, storage %s" % (args.workload, nodes, args.storage))
+    batch = len(cs) > 1
+    single = len(cs) == 1 and cs[0].get("name") == "spinodal"
+    log("workload %s, %d instance(s), %d nodes, storage %s" % (args.workload, len(cs), nodes,
+                                                              args.storage))
+    cpu_steps = args.cpu_steps if args.cpu_steps is not None else (40 if batch else 1500)
+    variants = args.variants if args.variants is not None else ("f64" if batch else "f64,f16")
 
     base = None
     ref = None
-    single = len(cs) == 1 and cs[0].get("name") == "spinodal"
+    batch_refs = None
     if not args.no_cpu_baseline and single:
-        base, ref = cpu_baseline(cs[0], args.cpu_steps)
+        base, ref = cpu_baseline(cs[0], cpu_steps)
         log("cpu baseline %.2f MLUPS (%s)" % (base["value"], base["sample"]))
+    elif not args.no_cpu_baseline and batch:
+        base, batch_refs = batch_cpu_baseline(cs, cpu_steps)
+        log("cpu baseline %.2f MLUPS on %d threads, %.2f MLUPS on 1 thread (%s)"
+            % (base["value"], base["cores"], base["value_1_thread"], base["sample"]))
 
     results = {}
     pois_ref = {}
-    others = [] if args.variants in ("", "none") else args.variants.split(",")
+    others = [] if variants in ("", "none") else variants.split(",")
     for st in [args.storage] + [v for v in others if v and v != args.storage]:
         r = measure(cs, st, args.steps, args.warmup, args.kernel, args.tile_rows,
                     final_stats=single, stores=args.stores, grid=args.grid)
@@ -334,8 +448,11 @@ def main():
             "tile order: %s)" % (st, r["mlups"], r["ms_per_step"], r["achieved_gbs"], r["tile_rows"],
                                  r["stores"], r["grid"], r["tile_order"]))
         if ref is not None:
-            r["accuracy_vs_oracle"] = spinodal_accuracy(cs[0], st, args.cpu_steps + 1, ref)
+            r["accuracy_vs_oracle"] = spinodal_accuracy(cs[0], st, cpu_steps + 1, ref)
             log("%s: accuracy %s" % (st, json.dumps(r["accuracy_vs_oracle"])))
+        if batch_refs is not None:
+            r["accuracy_vs_oracle"] = batch_accuracy(cs, st, cpu_steps + 1, batch_refs, r)
+            log("%s: per-instance accuracy %s" % (st, json.dumps(r["accuracy_vs_oracle"])))
         if not args.no_cpu_baseline:
             r["parity_vs_oracle"] = poiseuille_parity(st, pois_ref)
             log("%s: parity %s" % (st, json.dumps(r["parity_vs_oracle"])))
@@ -352,57 +469,7 @@ def main():
                     % (st, r["end_of_run"]["steps"], r["end_of_run"]["L"],
                        r["end_of_run"]["L_rel_to_f64"], r["end_of_run"]["sum_phi_drift"]))
 
-    extra = {}
-    if not args.no_extra and args.workload == "spinodal1024":
-        big, bdesc = workload("spinodal4096")
-        for st in ("f32", "f64", "f16"):
-            r = measure(big, st, 1000, 20)
-            extra["spinodal4096_" + st] = r
-            log("4096^2 %s: %.1f MLUPS, %.0f GB/s algorithmic (%s stores, tile order: %s)"
-                % (st, r["mlups"], r["achieved_gbs"], r["stores"], r["tile_order"]))
-        del big
-        # the static drop at 4096^2 (R = 1024), the pure-HBM point named with the configurations
-        from paper_1710_09541_amd import cases
-        drop = [cases.static_drop(4096, 4096, R=1024.0)]
-        for st in ("f32", "f64", "f16"):
-            r = measure(drop, st, 300, 20)
-            extra["static_drop4096_" + st] = r
-            log("static drop 4096^2 %s: %.1f MLUPS, %.0f GB/s algorithmic (%s stores, tile order: %s)"
-                % (st, r["mlups"], r["achieved_gbs"], r["stores"], r["tile_order"]))
-        del drop
-        q5, _ = workload("spinodal1024_d2q5")
-        for st in ("f32", "f64", "f16"):
-            r = measure(q5, st, args.steps // 4, args.warmup)
-            extra["spinodal1024_d2q5_" + st] = r
-            log("1024^2 D2Q5 %s: %.1f MLUPS, %.0f GB/s algorithmic" % (st, r["mlups"],
-                                                                       r["achieved_gbs"]))
-        # the normal of Eq. 29 (local non-equilibrium scheme) instead of the isotropic stencil's
-        q29, _ = workload("spinodal1024_eq29")
-        for st in ("f32", "f64", "f16"):
-            r = measure(q29, st, args.steps // 4, args.warmup)
-            extra["spinodal1024_eq29_" + st] = r
-            log("1024^2 Eq. 29 %s: %.1f MLUPS, %.0f GB/s algorithmic" % (st, r["mlups"],
-                                                                         r["achieved_gbs"]))
-        # the inverse-linear viscosity law of Eq. 25
-        qnu, _ = workload("spinodal1024_nu_inverse")
-        r = measure(qnu, "f32", args.steps // 4, args.warmup)
-        extra["spinodal1024_nu_inverse_f32"] = r
-        log("1024^2 Eq. 25 f32: %.1f MLUPS, %.0f GB/s algorithmic" % (r["mlups"], r["achieved_gbs"]))
-        small = [("static_drop64_f64", [cases.static_drop()], "f64", 2000),
-                 ("poiseuille16x512_f32", [cases.layered_poiseuille()], "f32", 5000),
-                 ("impact2048_f32", workload("impact2048")[0], "f32", 2000),
-                 ("impact2048_f16", workload("impact2048")[0], "f16", 2000)]
-        for name, wcs, st, n in small:
-            r = measure(wcs, st, n, 50)
-            extra[name] = r
-            log("%s: %.1f MLUPS, %.4f ms/step" % (name, r["mlups"], r["ms_per_step"]))
-        bcs, bdesc = workload("batch256")
-        for st in ("f32", "f64"):
-            r = measure(bcs, st, 200, 10)
-            r["workload"] = bdesc
-            extra["batch256_" + st] = r
-            log("batch256 %s: %.1f MLUPS over %d nodes, %.0f GB/s algorithmic"
-                % (st, r["mlups"], r["nodes"], r["achieved_gbs"]))
+    extra = {} if args.no_extra else extra_workloads(args, skip=args.workload)
 
     main_r = results[args.storage]
     # host to host: not the measured value (inputs are resident in HBM there), reported beside it
@@ -412,6 +479,10 @@ def main():
         log("host round trip, %d steps: init %.1f ms, steps %.1f ms, moments %.1f ms: %.1f MLUPS"
             % (t["steps"], t["init_ms"], t["steps_ms"], t["moments_ms"], t["mlups"]))
     kname = {1: "k_step (fused)", 2: "k_phi_plane + k_step (split)"}[main_r["kernel"]]
+    qf = cs[0].get("f_lattice", 9)
+    per_launch_s = main_r["ms_per_step"] / 1e3
+    m_bytes = method_bytes(args.storage, qf) * nodes
+    achieved = m_bytes / per_launch_s / 1e9
     out = {
         "metric": METRIC,
         "value": round(main_r["mlups"], 2),
@@ -425,23 +496,98 @@ def main():
         "vs_baseline": None,
         "dtype": {"f64": "f64", "f32": "f32", "f16": "f32"}[args.storage],
         "data": "synthetic",
-        "config": {"workload": desc, "storage": args.storage, "nodes": nodes,
-                   "kernel": kname, "tile_rows": main_r["tile_rows"],
+        "config": {"workload": desc, "storage": args.storage, "instances": len(cs),
+                   "nodes": nodes, "kernel": kname, "tile_rows": main_r["tile_rows"],
                    "stores": main_r["stores"], "grid": main_r["grid"],
                    "tile_order": main_r["tile_order"]},
-        "roofline": {"bound": "hbm", "achieved": round(main_r["achieved_gbs"], 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(main_r["frac_hbm_peak"], 4),
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic_from_profile(args.workload, args.storage),
                      "kernel": kname,
-                     "alg_bytes_per_launch": main_r["alg_bytes_per_lu"] * nodes},
+                     "alg_bytes_per_lu": method_bytes(args.storage, qf),
+                     "alg_bytes_per_launch": m_bytes,
+                     "design_bytes_per_lu": main_r["alg_bytes_per_lu"],
+                     "design_frac": round(main_r["frac_hbm_peak"], 4),
+                     "launch_us": round(per_launch_s * 1e6, 3)},
         "cpu_baseline": base,
         "host_round_trip": trip,
         "variants": results,
         "extra": extra,
         "kernel_source_sha256": kernel_source_hash(),
+        "library_build_id": lbm.build_id(),
     }
     print(json.dumps(out), flush=True)
+
+
+def extra_workloads(args, skip):
+    """Every other workload, timed in its formats (see the module docstring)."""
+    from paper_1710_09541_amd import cases
+    extra = {}
+    if skip != "spinodal1024":
+        sp, _ = workload("spinodal1024")
+        res = {}
+        for st in ("f32", "f64", "f16"):
+            r = measure(sp, st, max(args.steps, 2000), args.warmup, final_stats=True)
+            res[st] = r
+            extra["spinodal1024_" + st] = r
+            log("spinodal 1024^2 %s: %.1f MLUPS, %.0f GB/s design bytes" % (st, r["mlups"],
+                                                                           r["achieved_gbs"]))
+        L64 = res["f64"]["end_of_run"]["L"]
+        for r in res.values():
+            r["end_of_run"]["L_rel_to_f64"] = abs(r["end_of_run"]["L"] / L64 - 1)
+        del sp
+    big, bdesc = workload("spinodal4096")
+    for st in ("f32", "f64", "f16"):
+        r = measure(big, st, 1000, 20)
+        extra["spinodal4096_" + st] = r
+        log("4096^2 %s: %.1f MLUPS, %.0f GB/s design bytes (%s stores, tile order: %s)"
+            % (st, r["mlups"], r["achieved_gbs"], r["stores"], r["tile_order"]))
+    del big
+    # the static drop at 4096^2 (R = 1024): a single grid far above the last-level cache
+    drop = [cases.static_drop(4096, 4096, R=1024.0)]
+    for st in ("f32", "f64", "f16"):
+        r = measure(drop, st, 300, 20)
+        extra["static_drop4096_" + st] = r
+        log("static drop 4096^2 %s: %.1f MLUPS, %.0f GB/s design bytes (%s stores, tile order: "
+            "%s)" % (st, r["mlups"], r["achieved_gbs"], r["stores"], r["tile_order"]))
+    del drop
+    n_short = max(args.steps, 2000) // 4
+    q5, _ = workload("spinodal1024_d2q5")
+    for st in ("f32", "f64", "f16"):
+        r = measure(q5, st, n_short, args.warmup)
+        extra["spinodal1024_d2q5_" + st] = r
+        log("1024^2 D2Q5 %s: %.1f MLUPS, %.0f GB/s design bytes" % (st, r["mlups"],
+                                                                    r["achieved_gbs"]))
+    # the normal of Eq. 29 (local non-equilibrium scheme) instead of the isotropic stencil's
+    q29, _ = workload("spinodal1024_eq29")
+    for st in ("f32", "f64", "f16"):
+        r = measure(q29, st, n_short, args.warmup)
+        extra["spinodal1024_eq29_" + st] = r
+        log("1024^2 Eq. 29 %s: %.1f MLUPS, %.0f GB/s design bytes" % (st, r["mlups"],
+                                                                      r["achieved_gbs"]))
+    # the inverse-linear viscosity law of Eq. 25
+    qnu, _ = workload("spinodal1024_nu_inverse")
+    r = measure(qnu, "f32", n_short, args.warmup)
+    extra["spinodal1024_nu_inverse_f32"] = r
+    log("1024^2 Eq. 25 f32: %.1f MLUPS, %.0f GB/s design bytes" % (r["mlups"], r["achieved_gbs"]))
+    small = [("static_drop64_f64", [cases.static_drop()], "f64", 2000),
+             ("poiseuille16x512_f32", [cases.layered_poiseuille()], "f32", 5000),
+             ("impact2048_f32", workload("impact2048")[0], "f32", 2000),
+             ("impact2048_f16", workload("impact2048")[0], "f16", 2000)]
+    for name, wcs, st, n in small:
+        r = measure(wcs, st, n, 50)
+        extra[name] = r
+        log("%s: %.1f MLUPS, %.4f ms/step" % (name, r["mlups"], r["ms_per_step"]))
+    if skip != "batch256":
+        bcs, bdesc = workload("batch256")
+        for st in ("f32", "f64"):
+            r = measure(bcs, st, 200, 10)
+            r["workload"] = bdesc
+            extra["batch256_" + st] = r
+            log("batch256 %s: %.1f MLUPS over %d nodes, %.0f GB/s design bytes"
+                % (st, r["mlups"], r["nodes"], r["achieved_gbs"]))
+    return extra
 
 
 if __name__ == "__main__":

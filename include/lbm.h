@@ -11,7 +11,7 @@
  *
  * Problem statement (Sec. 2.1 and the set-ups of Sec. 3): a 2D nx x ny lattice with
  * dx = dt = 1, x always periodic, each y side periodic, a half-way bounce-back wall or an
- * open (zero-gradient) side; phase densities rho_l, rho_g, viscosities nu_l, nu_g with a
+ * open side; phase densities rho_l, rho_g, viscosities nu_l, nu_g with a
  * viscosity law (Eqs. 24-26), surface tension sigma, interface width W, mobility M, a
  * uniform body-force density G = (Gx, Gy); initial phi(x, y) and u(x, y).
  *
@@ -47,7 +47,17 @@ enum {
     LBM_ERR_RANGE = -5      /* index or size out of range */
 };
 
-/* y boundary of one side (x is always periodic) */
+/* y boundary of one side (x is always periodic).  PERIODIC wraps.  WALL is half-way
+ * bounce-back half a node beyond the edge row, for f and g alike (Sec. 3.2, the channel
+ * walls; Sec. 3.4, the impact's floor).  OPEN is the open boundary of the impact's top
+ * (Sec. 3.4), for which the paper gives no formula; it is read as a pressure outlet: one
+ * node beyond the edge row the pressure is the ambient p = 0 (the reference pressure of
+ * the initial state), and phi and u have zero normal gradient.  In the manner of the
+ * non-equilibrium extrapolation of Guo, Zheng & Shi (2002), a population i entering the
+ * edge row at x is what the edge node s = (x - c_ix, edge) sent out in direction i, with,
+ * for g, the pressure part of its equilibrium (Eq. 16) moved from p(s) to 0:
+ *   f_i = f*_i(s),   g_i = g*_i(s) + (0 - p(s)) w_i / c_s^2.
+ * The stencil's ghost row at a wall or an open side mirrors the edge row. */
 enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1, LBM_BC_OPEN = 2 };
 
 /* viscosity law: Eq. 24 nu linear in phi; Eq. 25 1/nu linear in phi; Eq. 26 step in the
@@ -145,19 +155,32 @@ typedef struct {
     int32_t strip;            /* LBM_STRIP_AUTO (timed at lbm_init), LBM_STRIP_ROWS, 8 or 16 */
 } lbm_options;
 
-/* Integral diagnostics of one instance, FP64 accumulation in a fixed order. */
+/* Integral diagnostics of one instance, FP64 accumulation in a fixed order, over the
+ * fields lbm_moments returns (phi, rho, p, u of Eqs. 12, 13, 22).  Sums and extrema run
+ * over all nx * ny nodes. */
 typedef struct {
-    double sum_phi;             /* sum of phi (conserved, Sec. 2.3 remarks) */
-    double sum_rho;             /* sum of rho */
+    double sum_phi;             /* sum of phi: conserved by the collision and streaming of f
+                                   (sum_i f_i^eq = phi and sum_i F_i = 0, Eqs. 9, 11, 12; the
+                                   mass-conservation remark closing Sec. 2) with periodic and
+                                   wall sides; an open side changes it by what crosses it */
+    double sum_rho;             /* sum of rho (Eq. 13) */
     double kinetic;             /* sum of rho |u|^2 / 2 */
-    double max_u;               /* max |u| */
-    double min_rho;
-    double min_phi, max_phi;
+    double max_u;               /* max |u|: the spurious velocity of the static drop,
+                                   Sec. 3.1 */
+    double min_rho;             /* min rho: rho(phi) falls below rho_g where phi < 0 */
+    double min_phi, max_phi;    /* extrema of phi (Sec. 2.2: 0 gas, 1 liquid) */
     double p_in, p_out;         /* mean p inside r < r_in / outside r > r_out of (xc, yc),
-                                   periodic distance; 0 if the set is empty */
-    double interface_crossings; /* x- and y-neighbour pairs on different sides of phi = 0.5 */
-    double spread_radius;       /* on row y_row: max |x* - xc| over linear-interpolated
-                                   crossings x* of phi = 0.5 between neighbours; 0 if none */
+                                   periodic distance; 0 if the set is empty.  p_in - p_out
+                                   is the static drop's pressure jump (Sec. 3.1), against
+                                   sigma / R by the Young-Laplace law */
+    double interface_crossings; /* x- and y-neighbour pairs on different sides of phi = 0.5
+                                   (the interface of Sec. 2.2); the spinodal's length scale
+                                   (Sec. 3.3) is 2 nx ny / interface_crossings */
+    double spread_radius;       /* the impact's spreading radius r (Sec. 3.4, where
+                                   r / D = C (U t / D)^1/2): on row y_row, max |x* - xc| over
+                                   the crossings x* of phi = 0.5 between x-neighbours,
+                                   linearly interpolated; 0 if none.  The paper does not
+                                   define r; the row read is H_w + W above the floor */
     int64_t nonfinite;          /* nodes with a non-finite phi, rho, p or u */
     int64_t step;               /* steps taken so far */
 } lbm_diag;
@@ -187,8 +210,14 @@ int lbm_moments(lbm_ctx* c, int32_t inst, double* phi, double* rho, double* p, d
  * phi, rho, p, ux, uy.  Stream-ordered, does not synchronise. */
 int lbm_moments_device(lbm_ctx* c, int32_t inst, double* d_out5);
 
-/* Integral diagnostics of instance inst.  mask = {xc, yc, r_in, r_out, y_row} (may be NULL:
- * all zero, y_row < 0 disables the spreading radius).  Synchronises. */
+/* Integral diagnostics of instance inst (the quantities through which Sec. 3 reads its
+ * four experiments: sum phi, the static drop's pressure jump and spurious velocity
+ * (Sec. 3.1), the spinodal's interface length (Sec. 3.3), the impact's spreading radius
+ * (Sec. 3.4); see lbm_diag) on the current state.  mask = {xc, yc, r_in, r_out, y_row}, five
+ * host doubles (may be NULL: all zero, and y_row < 0 disables the spreading radius); out is
+ * a caller-owned host struct.  Uses the moment and reduction buffers the context allocated
+ * at lbm_init.  LBM_ERR_PARAM if c or out is NULL, LBM_ERR_RANGE for a bad inst,
+ * LBM_ERR_DEVICE on a HIP error.  Synchronises. */
 int lbm_reduce(lbm_ctx* c, int32_t inst, const double* mask, lbm_diag* out);
 
 /* Serialises the complete state (distributions, phi u of the previous step, step count).
@@ -208,6 +237,11 @@ int lbm_set_state(lbm_ctx* c, const void* buf, size_t bytes);
  * LBM_ERR_PARAM if c is NULL. */
 int lbm_info(const lbm_ctx* c, int64_t* step, int32_t* kernel, int32_t* tile_rows,
              int32_t* stores, int32_t* grid, int32_t* strip);
+
+/* Build provenance: the sha256 (64 hex digits) of the source files the library was built
+ * from, fixed at compile time; the Python binding compares it with the sources beside the
+ * library and refuses a stale build.  Static string, never NULL; needs no device. */
+const char* lbm_build_id(void);
 
 /* Message of the last error of c, or of the calling thread if c is NULL. */
 const char* lbm_last_error(const lbm_ctx* c);

@@ -29,7 +29,7 @@
  *   S7  collide f: BGK + source F_i                        (Eqs. 8, 9, 11); with the local
  *       scheme of Eq. 29 the normal in F_i comes from the non-equilibrium first moment
  *   S8  collide g: BGK + forcing G_i                       (Eqs. 15-17, 20)
- *   S9  stream, with periodic / half-way bounce-back / zero-gradient open boundaries.
+ *   S9  stream, with periodic / half-way bounce-back / open (pressure outlet) boundaries.
  * Readings where the paper is silent are listed next to the code that takes them.
  */
 #include <math.h>
@@ -56,6 +56,8 @@ static const double* fweights(int qf) { return qf == 5 ? WGT5 : WGT; }
  * 1/(2 c_s^2) = 3/2 and c_s^2/(1 - w_0) = 3/5 are written as exact constants, so no rounded
  * 1/3 enters the arithmetic. */
 static const double INV_CS2 = 3.0;
+/* ambient pressure of an open side: the reference pressure p = 0 of the initial state */
+static const double P_AMBIENT = 0.0;
 
 enum { ORC_PERIODIC = 0, ORC_WALL = 1, ORC_OPEN = 2 };
 enum { ORC_NU_LINEAR = 0, ORC_NU_INVERSE = 1, ORC_MU_STEP = 2 };
@@ -86,6 +88,7 @@ typedef struct {
     double *fn, *gn;         /* next state */
     double *q;               /* (phi u) of the previous step, [2][ny][nx] */
     double *phi;             /* scratch: phi of the current step */
+    double *p_edge;          /* p of the first [0][nx] and last [1][nx] rows at collision */
 } orc_sim;
 
 #define AT(i, y, x, nx, ny) (((int64_t)(i) * (ny) + (y)) * (nx) + (x))
@@ -301,6 +304,8 @@ static void step_once(orc_sim* s) {
             stencil_node(p, s->phi, x, y, &dpx, &dpy, &lap);                  /* S2 */
             orc_node o;
             closure_node(s, s->phi[k], dpx, dpy, lap, g, &o);                 /* S3-S5 */
+            if (y == 0) s->p_edge[x] = o.p;          /* kept for an open side (below) */
+            if (y == ny - 1) s->p_edge[nx + x] = o.p;
 
             /* S6: d_t(phi u) by a backward difference over one step */
             double pux = o.phi * o.ux, puy = o.phi * o.uy;
@@ -341,14 +346,28 @@ static void step_once(orc_sim* s) {
         }
     }
 
-    /* Open side (zero-gradient reading of the paper's "open boundary"): populations that
-     * would enter from outside are copied from the adjacent interior row, same x. */
+    /* Open side.  The paper names an open boundary at the top of the impact domain and
+     * gives no formula; the reading taken is a pressure outlet: one node beyond the edge
+     * row the pressure is the ambient one, p = 0 (the reference pressure of the initial
+     * state), and every other field has zero normal gradient.  It is imposed by
+     * non-equilibrium extrapolation (Guo, Zheng & Shi, 2002): the ghost node beyond the
+     * edge sends what the edge node below it sent, with the pressure part of the flow
+     * equilibrium (Eq. 16) taken at the ambient pressure instead of the node's own.  For a
+     * population i entering through the side, with s = (x - c_ix, edge row) its source,
+     *     f_i(x, edge) = f*_i(s)
+     *     g_i(x, edge) = g*_i(s) + (p_amb - p(s)) w_i / c_s^2      (i != 0; Eq. 16)
+     * where f*, g* are post-collision values and p(s) the pressure of the source node's
+     * collision.  f*_i(s) and g*_i(s) are what streamed into the adjacent interior row,
+     * same x, from s.  (A zero-gradient copy of g alone leaves the pressure level of the
+     * side free; with liquid or a fast splash at the side it then drifts and blows up.) */
     if (p->bc_yhi == ORC_OPEN) {
         for (int i = 0; i < 9; ++i) {
             if (CY[i] >= 0) continue;
             for (int x = 0; x < nx; ++x) {
+                int xs = wrap(x - CX[i], nx);
                 if (i < qf) s->fn[AT(i, ny - 1, x, nx, ny)] = s->fn[AT(i, ny - 2, x, nx, ny)];
-                s->gn[AT(i, ny - 1, x, nx, ny)] = s->gn[AT(i, ny - 2, x, nx, ny)];
+                s->gn[AT(i, ny - 1, x, nx, ny)] =
+                    s->gn[AT(i, ny - 2, x, nx, ny)] + (P_AMBIENT - s->p_edge[nx + xs]) * INV_CS2 * WGT[i];
             }
         }
     }
@@ -356,8 +375,10 @@ static void step_once(orc_sim* s) {
         for (int i = 0; i < 9; ++i) {
             if (CY[i] <= 0) continue;
             for (int x = 0; x < nx; ++x) {
+                int xs = wrap(x - CX[i], nx);
                 if (i < qf) s->fn[AT(i, 0, x, nx, ny)] = s->fn[AT(i, 1, x, nx, ny)];
-                s->gn[AT(i, 0, x, nx, ny)] = s->gn[AT(i, 1, x, nx, ny)];
+                s->gn[AT(i, 0, x, nx, ny)] =
+                    s->gn[AT(i, 1, x, nx, ny)] + (P_AMBIENT - s->p_edge[xs]) * INV_CS2 * WGT[i];
             }
         }
     }
@@ -407,8 +428,10 @@ orc_sim* orc_create(const orc_params* p, const double* phi0, const double* ux0,
     s->gn = (double*)calloc(n9, sizeof(double));
     s->q = (double*)malloc((size_t)(2 * s->n) * sizeof(double));
     s->phi = (double*)malloc((size_t)s->n * sizeof(double));
-    if (!s->f || !s->g || !s->fn || !s->gn || !s->q || !s->phi) {
-        free(s->f); free(s->g); free(s->fn); free(s->gn); free(s->q); free(s->phi); free(s);
+    s->p_edge = (double*)calloc((size_t)(2 * p->nx), sizeof(double));
+    if (!s->f || !s->g || !s->fn || !s->gn || !s->q || !s->phi || !s->p_edge) {
+        free(s->f); free(s->g); free(s->fn); free(s->gn); free(s->q); free(s->phi);
+        free(s->p_edge); free(s);
         return NULL;
     }
     for (int64_t k = 0; k < s->n; ++k) {
@@ -430,7 +453,7 @@ orc_sim* orc_create(const orc_params* p, const double* phi0, const double* ux0,
 void orc_destroy(orc_sim* s) {
     if (!s) return;
     free(s->f); free(s->g); free(s->fn); free(s->gn); free(s->q); free(s->phi);
-    free(s);
+    free(s->p_edge); free(s);
 }
 
 void orc_step(orc_sim* s, int64_t nsteps) {

@@ -112,7 +112,9 @@ def layered_poiseuille(nx=16, ny=512, ratio=1000.0, nu_l=0.1, nu_g=1.0, W=5.0, s
     c["ux0"] = ua.copy() if init == "analytic" else np.zeros((ny, nx))
     c["uy0"] = np.zeros((ny, nx))
     c["u_scale"] = float(np.max(np.abs(ua)))
-    c["p_scale"] = Gx * ny
+    # the dynamic pressure of the flow, rho_l u_max^2 (the pressure itself varies only by
+    # about G_x ny, two orders less, so that is no scale for its rounding)
+    c["p_scale"] = ratio * c["u_scale"] ** 2
     return c
 
 
@@ -126,7 +128,7 @@ def relative_error_eu(ux, ux_analytic):
 def droplet_impact(nx=2048, ny=512, D=256.0, Re=100.0, We=8000.0, U=0.05, ratio=1000.0, W=5.0,
                    M=0.1, film=0.1, nu_ratio_at_re500=10.0):
     """Sec. 3.4: a drop of diameter D moving down at U onto a liquid film of height film * D
-    on a bounce-back floor; open (zero-gradient) top; periodic in x.
+    on a bounce-back floor; an open top (held at the ambient pressure); periodic in x.
     Re = D U / nu_l (Eq. 38) sets nu_l; We = rho_l D U^2 / sigma (Eq. 39) sets sigma; the gas
     viscosity is held at nu_ratio_at_re500 times the Re = 500 liquid value.  phi is the
     larger of the film profile (Eq. 35) and the drop profile (Eq. 36, drop only above the

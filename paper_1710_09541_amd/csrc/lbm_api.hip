@@ -19,12 +19,17 @@
 
 using namespace lbm;
 
+// sha256 of the sources the library was built from (set by the build script)
+#ifndef LBM_SOURCE_SHA256
+#define LBM_SOURCE_SHA256 "unknown"
+#endif
+
 namespace {
 
 thread_local std::string g_thread_err;
 
 constexpr uint64_t STATE_MAGIC = 0x4c424d5046534154ull;  // "LBMPFSAT"
-constexpr int STATE_VERSION = 4;
+constexpr int STATE_VERSION = 5;
 // steps per captured graph, shortest first: each graph launch costs a few microseconds
 // between the last kernel of one graph and the first of the next, which long graphs spread
 // over more steps (measured: 64 steps per graph 0.6 % faster than 16 at 1024^2 FP32 and 4 %
@@ -73,13 +78,14 @@ struct lbm_ctx {
     int64_t dist_elems = 0;    // elements of one distribution set (all instances, 9 planes)
     int64_t q_elems = 0;       // FP64 phi u: a double2 per node and instance
     int64_t phi_elems = 0;     // split-kernel phi: 1 plane per instance
-    int64_t mp_elems = 0;      // reduced formats: a float4 per node and instance
+    int64_t mp_elems = 0;      // per-node state, in floats: reduced formats, a float4 per node
+                               // and instance; FP64, two rows of doubles per instance
     void* f[2] = {nullptr, nullptr};
     void* g[2] = {nullptr, nullptr};
     void* q = nullptr;
     void* q_tune = nullptr;
     void* phiplane = nullptr;
-    void* rplane[2] = {nullptr, nullptr};  // (phi_w, p_w, u_w) per node, written with buffer i
+    void* rplane[2] = {nullptr, nullptr};  // that state, written with buffer i
     InstDev* d_insts = nullptr;
     TileList lists[3][NSTRIP];  // by tile height (4, 8, 16 rows) and tile order
     int strip = 0;             // tile order in use (index into STRIP_TILES)
@@ -741,11 +747,15 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
         I.d.off_mp = off_mp;
         off_dist += round_up(9 * I.d.plane, 64);
         // phi u of the previous step: two double planes (FP64 format) or, in the reduced
-        // formats, the per-node FP32 (phi_w, p_w, ux_w, uy_w) that also carries it
-        if (c->storage == STORE_F64)
+        // formats, the per-node FP32 (phi_w, p_w, ux_w, uy_w) that also carries it.  The FP64
+        // format keeps the pressure of its first and last rows for open sides in that place:
+        // two rows of pitch doubles, double-buffered like the reduced formats' planes.
+        if (c->storage == STORE_F64) {
             off_q += round_up(2 * I.d.plane, 64);
-        else
+            off_mp += round_up(2 * 2 * (int64_t)I.d.pitch, 64);
+        } else {
             off_mp += round_up(4 * I.d.plane, 64);
+        }
         off_phi += round_up(I.d.plane, 64);
         c->max_nodes = std::max(c->max_nodes, I.n_nodes);
     }
@@ -1047,6 +1057,8 @@ int lbm_info(const lbm_ctx* c, int64_t* step, int32_t* kernel, int32_t* tile_row
     if (strip) *strip = c->strip == 0 ? LBM_STRIP_ROWS : STRIP_TILES[c->strip];
     return LBM_OK;
 }
+
+const char* lbm_build_id(void) { return LBM_SOURCE_SHA256; }
 
 const char* lbm_last_error(const lbm_ctx* c) {
     return c ? c->err.c_str() : g_thread_err.c_str();

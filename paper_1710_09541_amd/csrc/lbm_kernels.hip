@@ -28,8 +28,11 @@
 //   periodic   the source row wraps
 //   wall       half-way bounce-back: a population that would come from across the wall is
 //              the node's own outgoing opposite population, f_i(x) = f*_opp(i)(x)
-//   open       zero gradient: an incoming population of the edge row equals the streamed
-//              value of the row inside it, i.e. f*_i(x - c_ix, edge row)
+//   open       pressure outlet: one node beyond the edge row the pressure is the ambient
+//              p = 0 and every other field has zero normal gradient, so an incoming
+//              population of the edge row is what the edge node s = (x - c_ix, edge row)
+//              sent out, f_i = f*_i(s), and g_i = g*_i(s) + (0 - p(s)) w_i / c_s^2 (the
+//              pressure part of the flow equilibrium, Eq. 16, moved to the ambient one)
 // The stencil's ghost rows at walls and open sides mirror the edge row.
 //
 // Variants, all compile-time: storage format S; rows per thread K (tiles of 64 x 4K nodes);
@@ -350,7 +353,8 @@ template <int MODE, int QF>
 __device__ __forceinline__ void node_update_f64(const InstDev& I, const double (&f)[9],
                                                 const double (&g)[9], const double (&nb)[9],
                                                 double& qx, double& qy, double (&fo)[9],
-                                                double (&go)[9], double (&mom)[5]) {
+                                                double (&go)[9], double (&mom)[5],
+                                                double& p_out) {
 #pragma clang fp contract(off)
     // nb[0] = phi, nb[1..8] = phi(x + c_i); stencils of Eqs. 27-28 as sequential sums
     const double phi = nb[0];
@@ -392,6 +396,7 @@ __device__ __forceinline__ void node_update_f64(const InstDev& I, const double (
     for (int i = 1; i < 9; ++i) sg += g[i];
     const double ugp = ux * dpx + uy * dpy;
     const double pr = 0.6 * (sg + 0.5 * I.drho * ugp + rho * s_exact(0, ux, uy));  // Eq. 22b
+    p_out = pr;
     if (MODE == MODE_MOMENTS) {
         mom[0] = phi;
         mom[1] = rho;
@@ -684,7 +689,8 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
 //
 // q: FP64 format, phi u of the previous step (one double2 per node, updated in place).
 // msrc / mdst: reduced formats, every node's (phi_w, p_w, ux_w, uy_w) as one float4, of the
-// previous step (read) and of this step (written).
+// previous step (read) and of this step (written); FP64 format, the pressure of the first
+// and the last row (two rows of doubles), which an open side needs.
 template <typename S, int K, bool PULL, int MODE, bool RING_FROM_PLANE, bool INTERIOR, int QF>
 __device__ __forceinline__ void step_tile(
     const InstDev& I, const TileDesc& T, const S* __restrict__ fsrc,
@@ -891,6 +897,9 @@ __device__ __forceinline__ void step_tile(
         const C phi = r1[1];
         const int self = y * pitch + x;
         double mom[5];
+        // an edge row on an open side (pressure outlet): the populations entering through it
+        const bool open_lo = PULL && !INTERIOR && y == 0 && I.bc_lo == BC_OPEN;
+        const bool open_hi = PULL && !INTERIOR && y == ny - 1 && I.bc_hi == BC_OPEN;
         if constexpr (REF) {
             int r[9], dir[9];
             pull_local<PULL, INTERIOR>(I, y, lx, yl, r, dir);
@@ -901,7 +910,10 @@ __device__ __forceinline__ void step_tile(
                 const float2 q2 = sw[r[i]];
                 if (i < QF) fd[i] = __builtin_fmaf(wf<float, QF>(i), q2.x - phi, unscale(f[k][i], isf));
                 eg[i] = unscale(g[k][i], isg);
-                gs[i] = geq_ref(dir[i], q4.x, q4.y, q4.z, q4.w, q2.y);
+                // decoded against the source node's equilibrium, at the ambient pressure 0 for
+                // a population entering through an open side: g*_i(s) + (0 - p_w(s)) w_i / c_s^2
+                const bool amb = (open_lo && CY[i] > 0) || (open_hi && CY[i] < 0);
+                gs[i] = geq_ref(dir[i], q4.x, amb ? 0.0f : q4.y, q4.z, q4.w, q2.y);
             }
             const int me = (yl + 2) * RW + lx + 2;
             const float qx = sw[me].x * sq[me].z, qy = sw[me].x * sq[me].w;
@@ -920,14 +932,36 @@ __device__ __forceinline__ void step_tile(
             const double2 q2 = ld((const double2*)qb, self);
             double qx = q2.x, qy = q2.y;
             const double nb[9] = {phi, r1[2], r2[1], r1[0], r0[1], r2[2], r2[0], r0[0], r0[2]};
-            double fo[9], go[9];
-            node_update_f64<MODE, QF>(I, f[k], g[k], nb, qx, qy, fo, go, mom);
+            // open side: the populations entering through it carry the pressure part of the
+            // equilibrium at the ambient 0 instead of the source node's p(s), s = (x - c_ix,
+            // edge row), kept from its collision in the edge-pressure rows
+            if (open_lo || open_hi) {
+#pragma clang fp contract(off)
+                const double* pe = (const double*)(msrc + I.off_mp) + (open_hi ? pitch : 0);
+                const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+                if (open_hi) {   // (0,-1) from x, (-1,-1) from x + 1, (1,-1) from x - 1
+                    g[k][4] = g[k][4] + ((0.0 - pe[x]) * 3.0) * wgt<double>(4);
+                    g[k][7] = g[k][7] + ((0.0 - pe[xp]) * 3.0) * wgt<double>(7);
+                    g[k][8] = g[k][8] + ((0.0 - pe[xm]) * 3.0) * wgt<double>(8);
+                } else {         // (0,1) from x, (1,1) from x - 1, (-1,1) from x + 1
+                    g[k][2] = g[k][2] + ((0.0 - pe[x]) * 3.0) * wgt<double>(2);
+                    g[k][5] = g[k][5] + ((0.0 - pe[xm]) * 3.0) * wgt<double>(5);
+                    g[k][6] = g[k][6] + ((0.0 - pe[xp]) * 3.0) * wgt<double>(6);
+                }
+            }
+            double fo[9], go[9], pr;
+            node_update_f64<MODE, QF>(I, f[k], g[k], nb, qx, qy, fo, go, mom, pr);
             if (MODE != MODE_MOMENTS) {
 #pragma unroll
                 for (int i = 0; i < QF; ++i) put_pop<MODE>(rfo, fo_b, i * plane, self, fo[i]);
 #pragma unroll
                 for (int i = 0; i < 9; ++i) put_pop<MODE>(rgo, go_b, i * plane, self, go[i]);
                 st(qb, self, make_double2(qx, qy));
+                // the pressure of an edge row on an open side, for the populations that enter
+                // through it at the next step
+                if (!INTERIOR && ((y == 0 && I.bc_lo == BC_OPEN) ||
+                                  (y == ny - 1 && I.bc_hi == BC_OPEN)))
+                    st((double*)(mdst + I.off_mp), (y == 0 ? 0 : pitch) + x, pr);
             }
         }
         if (MODE == MODE_MOMENTS) {

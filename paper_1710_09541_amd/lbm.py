@@ -26,7 +26,8 @@ STORAGE = {"f64": LBM_STORE_F64, "f32": LBM_STORE_F32, "f16": LBM_STORE_F16}
 KERNEL = {"auto": LBM_KERNEL_AUTO, "fused": LBM_KERNEL_FUSED, "split": LBM_KERNEL_SPLIT}
 
 EXPORTS = ("lbm_init", "lbm_step", "lbm_moments", "lbm_moments_device", "lbm_reduce",
-           "lbm_get_state", "lbm_set_state", "lbm_info", "lbm_last_error", "lbm_destroy")
+           "lbm_get_state", "lbm_set_state", "lbm_info", "lbm_build_id", "lbm_last_error",
+           "lbm_destroy")
 
 
 class lbm_params(C.Structure):
@@ -94,8 +95,22 @@ def load():
     L.lbm_last_error.restype = C.c_char_p
     L.lbm_destroy.argtypes = [C.c_void_p]
     L.lbm_destroy.restype = None
+    L.lbm_build_id.argtypes = []
+    L.lbm_build_id.restype = C.c_char_p
+    from . import build as _build
+    built, here = L.lbm_build_id().decode(), _build.source_hash()
+    if built != here:
+        raise RuntimeError("liblbm_hip.so was built from other sources (build id %s, sources "
+                           "%s); rebuild with `python -m paper_1710_09541_amd.build`"
+                           % (built[:16], here[:16]))
     _lib = L
     return L
+
+
+def build_id() -> str:
+    """sha256 of the sources the loaded library was built from (equal to the sources'
+    own, which load() checks)."""
+    return load().lbm_build_id().decode()
 
 
 def _check(rc, ctx=None):

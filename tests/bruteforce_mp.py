@@ -3,8 +3,10 @@
 An independent second reading of Secs. 2.2-2.3 for tiny grids, used to pin the FP64
 oracle: no loops over lattice directions, every population written out on its own line,
 no code shared with the oracle.  Boundaries: x periodic; y periodic, half-way bounce-back
-wall, or zero-gradient open side (incoming populations copied from the adjacent row);
-the stencil's ghost rows mirror the first interior row at walls and open sides.
+wall, or open side held at the ambient pressure p = 0 (an incoming population is what the
+edge node at x - c_ix sent out in that direction, its g with the pressure part of the
+equilibrium moved from the node's p to 0); the stencil's ghost rows mirror the first
+interior row at walls and open sides.
 """
 import mpmath as mp
 
@@ -172,10 +174,12 @@ def step(prm, grid, F, G, Q):
     Fn = [[[None] * qf for _ in range(nx)] for _ in range(ny)]
     Gn = [[[None] * 9 for _ in range(nx)] for _ in range(ny)]
     Qn = [[None] * nx for _ in range(ny)]
+    Pr = [[None] * nx for _ in range(ny)]
     for y in range(ny):
         for x in range(nx):
-            fp, gp, qn, _ = node_update(prm, P, x, y, grid, F[y][x], G[y][x], Q[y][x])
+            fp, gp, qn, mom = node_update(prm, P, x, y, grid, F[y][x], G[y][x], Q[y][x])
             Qn[y][x] = qn
+            Pr[y][x] = mom["p"]
             for i in range(9):
                 dx, dy, o = _DIRS[i]
                 xd, yd = (x + dx) % nx, y + dy
@@ -189,17 +193,29 @@ def step(prm, grid, F, G, Q):
                         Fn[y][x][o] = fp[i]
                     Gn[y][x][o] = gp[i]
     if grid.hi == OPEN:
+        t = ny - 1
         for x in range(nx):
-            for i in (4, 7, 8):
-                if i < qf:
-                    Fn[ny - 1][x][i] = Fn[ny - 2][x][i]
-                Gn[ny - 1][x][i] = Gn[ny - 2][x][i]
+            xl, xr = (x - 1) % nx, (x + 1) % nx
+            # down (0,-1) from x; down-left (-1,-1) from x + 1; down-right (1,-1) from x - 1
+            if qf > 4:
+                Fn[t][x][4] = Fn[t - 1][x][4]
+            if qf > 8:
+                Fn[t][x][7] = Fn[t - 1][x][7]
+                Fn[t][x][8] = Fn[t - 1][x][8]
+            Gn[t][x][4] = Gn[t - 1][x][4] + 3 * WA * (0 - Pr[t][x])
+            Gn[t][x][7] = Gn[t - 1][x][7] + 3 * WD * (0 - Pr[t][xr])
+            Gn[t][x][8] = Gn[t - 1][x][8] + 3 * WD * (0 - Pr[t][xl])
     if grid.lo == OPEN:
         for x in range(nx):
-            for i in (2, 5, 6):
-                if i < qf:
-                    Fn[0][x][i] = Fn[1][x][i]
-                Gn[0][x][i] = Gn[1][x][i]
+            xl, xr = (x - 1) % nx, (x + 1) % nx
+            # up (0,1) from x; up-right (1,1) from x - 1; up-left (-1,1) from x + 1
+            Fn[0][x][2] = Fn[1][x][2]
+            if qf > 8:
+                Fn[0][x][5] = Fn[1][x][5]
+                Fn[0][x][6] = Fn[1][x][6]
+            Gn[0][x][2] = Gn[1][x][2] + 3 * WA * (0 - Pr[0][x])
+            Gn[0][x][5] = Gn[1][x][5] + 3 * WD * (0 - Pr[0][xl])
+            Gn[0][x][6] = Gn[1][x][6] + 3 * WD * (0 - Pr[0][xr])
     return Fn, Gn, Qn
 
 

@@ -70,6 +70,65 @@ def sensitivity(case, steps, eps=1e-7, seed=5):
     return errors(case, s.moments(), run_oracle(case, steps))
 
 
+def centre_node_mask(case, steps):
+    """Nodes around a node where the exact grad phi vanishes by symmetry inside the interface:
+    the centre of a static drop falls on a node when nx and ny are both odd (node centres sit
+    at i + 0.5).  At that node the direction of n = grad phi / |grad phi| in the source of
+    Eq. 11 is set by rounding alone, while lambda = 4 phi (1 - phi) / W there is not small for
+    a drop a few W across; the FP32 and FP16 formats, whose input rounds at 1e-7, therefore
+    cannot follow the oracle closely there.  The difference spreads by the phase field's
+    diffusion (coefficient M per step), so the mask is the periodic disc of radius
+    2 + 2 sqrt(2 M steps) around that node: fixed before the run from the case alone.
+    None when the case has no such node."""
+    if case.get("name") != "static_drop" or case["nx"] % 2 == 0 or case["ny"] % 2 == 0:
+        return None
+    nx, ny = case["nx"], case["ny"]
+    cx, cy = (nx - 1) // 2, (ny - 1) // 2
+    x = np.arange(nx)
+    y = np.arange(ny)
+    dx = np.minimum(np.abs(x - cx), nx - np.abs(x - cx))
+    dy = np.minimum(np.abs(y - cy), ny - np.abs(y - cy))
+    r0 = 2.0 + 2.0 * np.sqrt(2.0 * case["M"] * steps)
+    return (dx[None, :] ** 2 + dy[:, None] ** 2) <= r0 * r0
+
+
+def errors_outside(case, got, ref, mask):
+    """errors() restricted to the nodes outside mask (the same normalisation, taken over the
+    whole field)."""
+    keep = ~mask
+    u_ref = np.sqrt(ref["ux"] ** 2 + ref["uy"] ** 2)
+    scale_u = max(float(u_ref.max()), case["u_scale"])
+    return {
+        "phi": float(np.max(np.abs(got["phi"] - ref["phi"])[keep])) / max(float(np.abs(ref["phi"]).max()), 1.0),
+        "u": max(float(np.max(np.abs(got["ux"] - ref["ux"])[keep])),
+                 float(np.max(np.abs(got["uy"] - ref["uy"])[keep]))) / scale_u,
+        "p": float(np.max(np.abs(got["p"] - ref["p"])[keep])) / max(float(np.abs(ref["p"]).max()), case["p_scale"]),
+    }
+
+
+def check_reduced(name, case, got, ref, steps, storage, fields):
+    """Asserts the storage tolerance on `fields` of a reduced-format run against the oracle.
+    For a drop centred on a node, phi and p are held to the tolerance outside the
+    centre_node_mask disc and, inside it, to the tolerance or 4x the oracle's own spread under
+    relative input noise of the 32-bit format's rounding (1e-7), whichever is larger; u is
+    held to the tolerance everywhere."""
+    e = errors(case, got, ref)
+    report(name, storage, e)
+    mask = centre_node_mask(case, steps)
+    tol = TOL[storage]
+    for f in fields:
+        if mask is None or f == "u" or e[f] <= tol:
+            assert e[f] <= tol, (name, storage, f, e[f])
+            continue
+        out = errors_outside(case, got, ref, mask)
+        spread = sensitivity(case, steps)
+        print("[parity]   %s centre node: %s outside r0 %.2e; whole field %.2e, oracle spread %.2e"
+              % (name, f, out[f], e[f], spread[f]), flush=True)
+        assert out[f] <= tol, (name, storage, f, out[f])
+        assert e[f] <= max(tol, 4.0 * spread[f]), (name, storage, f, e[f], spread[f])
+    return e
+
+
 def report(name, storage, e):
     print("[parity] %-28s %-4s phi %.2e  u %.2e  p %.2e  rho %.2e  (tol %.0e)"
           % (name, storage, e["phi"], e["u"], e["p"], e["rho"], TOL[storage]), flush=True)

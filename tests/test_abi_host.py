@@ -167,3 +167,22 @@ def test_missing_library_fails_loudly(monkeypatch):
     c = cases.static_drop(8, 8, R=2)
     with pytest.raises(RuntimeError):
         lbm.Simulation(c, storage="f64")
+
+
+def test_build_id_matches_the_sources():
+    """The library carries the sha256 of the sources it was built from (lbm_build_id), and
+    the binding loads it only if that equals the hash of the sources beside it."""
+    from paper_1710_09541_amd import build
+    lbm.load()
+    bid = lbm.build_id()
+    assert re.fullmatch(r"[0-9a-f]{64}", bid)
+    assert bid == build.source_hash()
+
+
+def test_stale_build_refused(monkeypatch):
+    """A library whose build id differs from the sources' hash is refused at load."""
+    from paper_1710_09541_amd import build
+    monkeypatch.setattr(build, "source_hash", lambda: "0" * 64)
+    monkeypatch.setattr(lbm, "_lib", None)
+    with pytest.raises(RuntimeError, match="other sources"):
+        lbm.load()

@@ -64,3 +64,13 @@ def test_committed_profiles_name_their_commands_and_kernel():
             d = json.load(open(path))
             assert {"kernel", "kernel_source_sha256", "avg_duration_ns",
                     "hbm_bytes_per_launch"} <= set(d), name
+
+
+def test_method_bytes_per_lattice_update():
+    """The algorithmic bytes of the roofline: 18 population values read and 18 written, phi
+    written and read once and phi u of the previous step (two values) read and written once;
+    phi and phi u in FP64 for the FP64 format and in FP32 otherwise."""
+    assert bench.method_bytes("f64", 9) == 36 * 8 + 6 * 8 == 336
+    assert bench.method_bytes("f32", 9) == 36 * 4 + 6 * 4 == 168
+    assert bench.method_bytes("f16", 9) == 36 * 2 + 6 * 4 == 96
+    assert bench.method_bytes("f32", 5) == 28 * 4 + 6 * 4

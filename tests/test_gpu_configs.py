@@ -8,7 +8,7 @@ import pytest
 from oracle import diag
 from oracle.oracle import OracleSim
 from paper_1710_09541_amd import cases, lbm
-from tests.parity import TOL, errors, paper_value, report, run_oracle, sensitivity
+from tests.parity import TOL, check_reduced, errors, paper_value, report, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -55,28 +55,41 @@ def test_poiseuille_50000_steps(storage):
     assert abs(eu / eu_ref - 1) <= LONG_EU[storage]
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
-@pytest.mark.parametrize("Re,t_end", [(20.0, 3.0), (100.0, 2.0)])
-def test_impact_spreading_radius(storage, Re, t_end):
-    """Sec. 3.4 at the oracle's size (512 x 128, D = 64): the spreading radius r(t) on the
-    row y = H_w + W at t* = tU/D = 0.5, 1, 2 (and 3) within 2 % of the oracle's.  (At this
-    resolution the oracle itself does not stay finite to t* = 3 at Re = 100.)"""
+@pytest.mark.parametrize("Re", [20.0, 100.0, 500.0])
+def test_impact_oracle_size_to_t5(Re):
+    """Sec. 3.4 at the oracle's size (512 x 128, D = 64, We = 8000, ratio 1000, open top
+    held at the ambient pressure) to t* = tU/D = 5 at each Re of the paper: the spreading
+    radius r(t) on the row y = H_w + W at t* = 0.5, 1, 2, 3, 4, 5 against the oracle's.
+    FP64 repeats the oracle's arithmetic, so its radius and, at t* = 5, every field are
+    bitwise equal; FP32 and FP16 storage within 1 % and 2 % of the oracle's radius."""
     c = cases.droplet_impact(512, 128, D=64, Re=Re)
     T = c["D"] / c["U"]
-    times = [t for t in (0.5, 1.0, 2.0, 3.0) if t <= t_end]
     o = OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
-    with lbm.Simulation(c, storage=storage) as sim:
-        for t in times:
+    sims = {st: lbm.Simulation(c, storage=st) for st in ("f64", "f32", "f16")}
+    try:
+        for t in (0.5, 1.0, 2.0, 3.0, 4.0, 5.0):
             n = int(round(t * T))
             o.step(n - o.steps)
-            sim.step(n - sim.info()["step"])
-            r_ref = diag.diagnostics(o.moments(), c["rho_l"], c["rho_g"], c["mask"],
-                                     periodic_y=False)["spread_radius"]
-            d = sim.reduce()
-            print("[spreading] Re %g %s t*=%.1f: r/D %.4f vs oracle %.4f"
-                  % (Re, storage, t, d["spread_radius"] / c["D"], r_ref / c["D"]), flush=True)
-            assert d["nonfinite"] == 0
-            assert abs(d["spread_radius"] / r_ref - 1) < 0.02
+            m = o.moments()
+            r_ref = diag.diagnostics(m, c["rho_l"], c["rho_g"], c["mask"],
+                                     periodic_y=False)["spread_radius"] / c["D"]
+            r = {}
+            for st, sim in sims.items():
+                sim.step(n - sim.info()["step"])
+                d = sim.reduce()
+                assert d["nonfinite"] == 0, (st, t)
+                r[st] = d["spread_radius"] / c["D"]
+            print("[impact 512x128] Re %g t*=%.1f: r/D oracle %.5f f64 %.5f f32 %.5f f16 %.5f"
+                  % (Re, t, r_ref, r["f64"], r["f32"], r["f16"]), flush=True)
+            assert r["f64"] == r_ref
+            assert abs(r["f32"] / r_ref - 1) < 0.01
+            assert abs(r["f16"] / r_ref - 1) < 0.02
+        e = errors(c, sims["f64"].moments(), m)
+        report("impact 512x128 Re%g t*=5" % Re, "f64", e)
+        assert max(e.values()) == 0.0
+    finally:
+        for sim in sims.values():
+            sim.close()
 
 
 def test_batch_16_instances_1000_steps():
@@ -87,13 +100,9 @@ def test_batch_16_instances_1000_steps():
         sim.step(1000)
         got = [sim.moments(k) for k in range(len(batch))]
     for k, c in enumerate(batch):
-        e = errors(c, got[k], run_oracle(c, 1000))
-        report("batch16 inst %d %dx%d" % (k, c["nx"], c["ny"]), "f32", e)
-        assert e["u"] <= TOL["f32"]
-        bound = TOL["f32"]
-        if e["phi"] > bound:
-            bound = max(bound, 4.0 * sensitivity(c, 1000)["phi"])
-        assert e["phi"] <= bound
+        fields = ("phi", "u", "p") if c["name"] == "static_drop" else ("phi", "u")
+        check_reduced("batch16 inst %d %dx%d" % (k, c["nx"], c["ny"]), c, got[k],
+                      run_oracle(c, 1000), 1000, "f32", fields)
 
 
 def _length(phi):
@@ -129,13 +138,15 @@ def test_spinodal_1024_20000_steps_reduced_vs_fp64():
             sim.close()
 
 
-def test_impact_full_size_spreading_reduced_vs_fp64():
-    """The impact at full size (2048 x 512, D = 256, Re = 100) to t* = 5 (25,600 steps): the
-    spreading radius of FP32 and FP16 storage against the FP64 format at t* = 0.5 ... 5; and
-    the prefactor C of r/D = C sqrt(t*) (Sec. 3.4), fitted to the FP64 run over t* = 0.5 ... 2
-    (the paper gives no window), within 10 % of the paper's 1.35.  (The FP64 format repeats
-    the oracle's arithmetic bit for bit, so this pins the method at the paper's scale.)"""
-    c = cases.droplet_impact(2048, 512, D=256, Re=100)
+@pytest.mark.parametrize("Re", [20.0, 100.0])
+def test_impact_full_size_spreading_reduced_vs_fp64(Re):
+    """The impact as specified (2048 x 512, D = 256, film 0.1 D, We = 8000, ratio 1000, open
+    top) to t* = 5 (25,600 steps) at each Re: every format stays finite, and the spreading
+    radius of FP32 and FP16 storage stays within 1 % and 2 % of the FP64 format's at
+    t* = 0.5 ... 5.  At Re = 100, the prefactor C of r/D = C sqrt(t*) (Sec. 3.4), fitted to
+    the FP64 run over t* = 0.5 ... 2 (the paper gives no window), lies within 10 % of the
+    paper's 1.35.  (The FP64 format repeats the oracle's arithmetic bit for bit.)"""
+    c = cases.droplet_impact(2048, 512, D=256, Re=Re)
     T = c["D"] / c["U"]
     sims = {st: lbm.Simulation(c, storage=st) for st in ("f64", "f32", "f16")}
     ratios = []
@@ -145,10 +156,10 @@ def test_impact_full_size_spreading_reduced_vs_fp64():
             for st, sim in sims.items():
                 sim.step(int(round(t * T)) - sim.info()["step"])
                 d = sim.reduce()
-                assert d["nonfinite"] == 0
+                assert d["nonfinite"] == 0, (st, t)
                 r[st] = d["spread_radius"] / c["D"]
-            print("[spreading 2048x512] t*=%.1f: r/D f64 %.4f f32 %.4f f16 %.4f"
-                  % (t, r["f64"], r["f32"], r["f16"]), flush=True)
+            print("[spreading 2048x512] Re %g t*=%.1f: r/D f64 %.4f f32 %.4f f16 %.4f"
+                  % (Re, t, r["f64"], r["f32"], r["f16"]), flush=True)
             assert abs(r["f32"] / r["f64"] - 1) < 0.01
             assert abs(r["f16"] / r["f64"] - 1) < 0.02
             ratios.append(r["f64"] / np.sqrt(t))
@@ -156,18 +167,60 @@ def test_impact_full_size_spreading_reduced_vs_fp64():
         for sim in sims.values():
             sim.close()
     C_early = float(np.mean(ratios[:3]))
-    print("[spreading 2048x512] C (FP64) over t* = 0.5-2: %.3f, over 0.5-5: %.3f; r/D / sqrt(t*): %s"
-          % (C_early, float(np.mean(ratios)), " ".join("%.3f" % v for v in ratios)), flush=True)
-    assert abs(C_early / paper_value("spreading_prefactor_C") - 1) < 0.1
+    print("[spreading 2048x512] Re %g: C (FP64) over t* = 0.5-2: %.3f, over 0.5-5: %.3f; "
+          "r/D / sqrt(t*): %s" % (Re, C_early, float(np.mean(ratios)),
+                                  " ".join("%.3f" % v for v in ratios)), flush=True)
+    if Re == 100.0:
+        assert abs(C_early / paper_value("spreading_prefactor_C") - 1) < 0.1
+
+
+def test_impact_full_size_re500():
+    """The impact as specified at Re = 500 (2048 x 512, D = 256, film 0.1 D, nu_l = 0.0256,
+    tau_l = 0.577).  FP32 and FP16 storage track the FP64 format's spreading radius within
+    1 % and 2 % at t* = 0.5 and 1.  Shortly after, the two splash sheets meet at the periodic
+    seam (t* ~ 1.3) and throw up gas jets of |u| ~ 0.3; from there the three runs separate,
+    and the flow is chaotic and at the edge of the scheme's stability: of runs started from
+    phi0 perturbed by 1e-4 relative, about half go non-finite between t* = 1.8 and 5, in FP64
+    as in the reduced formats (measured on MI355X: FP64 4 of 8, FP32 3 of 8).  The FP64
+    format repeats the oracle's arithmetic bit for bit, and its unperturbed run, the
+    oracle's, stays finite to t* = 5 (25,600 steps) with the splash crossing the open top;
+    that is asserted, the reduced formats' runs past t* = 1 are not."""
+    c = cases.droplet_impact(2048, 512, D=256, Re=500.0)
+    T = c["D"] / c["U"]
+    sims = {st: lbm.Simulation(c, storage=st) for st in ("f64", "f32", "f16")}
+    try:
+        for t in (0.5, 1.0):
+            r = {}
+            for st, sim in sims.items():
+                sim.step(int(round(t * T)) - sim.info()["step"])
+                d = sim.reduce()
+                assert d["nonfinite"] == 0, (st, t)
+                r[st] = d["spread_radius"] / c["D"]
+            print("[spreading 2048x512] Re 500 t*=%.1f: r/D f64 %.4f f32 %.4f f16 %.4f"
+                  % (t, r["f64"], r["f32"], r["f16"]), flush=True)
+            assert abs(r["f32"] / r["f64"] - 1) < 0.01
+            assert abs(r["f16"] / r["f64"] - 1) < 0.02
+        sim = sims["f64"]
+        s0 = c["phi0"].sum()
+        for t in (2.0, 3.0, 4.0, 5.0):
+            sim.step(int(round(t * T)) - sim.info()["step"])
+            d = sim.reduce()
+            print("[spreading 2048x512] Re 500 t*=%.1f: FP64 r/D %.4f max|u| %.3f sum phi %.6f of "
+                  "the start" % (t, d["spread_radius"] / c["D"], d["max_u"], d["sum_phi"] / s0),
+                  flush=True)
+            assert d["nonfinite"] == 0, t
+            assert d["max_u"] < 5 * c["U"]
+    finally:
+        for sim in sims.values():
+            sim.close()
 
 
 def test_impact_re500_paper_geometry_reduced_vs_fp64():
     """Sec. 3.4 at Re = 500 in the paper's own set-up: 1500 x 500, R = 100, film H_w = 0.1 H
-    = 50, so nu_l = DU/Re = 0.02 and nu_g = 10 nu_l.  To t* = 2 (8000 steps), before the
-    splash sheets reach the open top, every format stays finite and FP32 and FP16 storage
-    track the FP64 format (which repeats the oracle's arithmetic bit for bit) in the
-    spreading radius.  Past t* ~ 2.1 the sheets cross the zero-gradient top row and the run
-    loses stability in every format; that range is not asserted here."""
+    = 50, so nu_l = DU/Re = 0.02 and nu_g = 10 nu_l.  FP64 equals the oracle after 100
+    steps; to t* = 5 (20,000 steps), with the splash sheets crossing the open top from
+    t* ~ 2.1, every format stays finite and FP32 and FP16 storage track the FP64 format in
+    the spreading radius (1 % and 2 %)."""
     c = cases.droplet_impact(1500, 500, D=200, Re=500, film=0.25)
     assert c["Hw"] == 50.0 and abs(c["nu_l"] - 0.02) < 1e-15
     with lbm.Simulation(c, storage="f64") as sim:
@@ -178,7 +231,7 @@ def test_impact_re500_paper_geometry_reduced_vs_fp64():
     T = c["D"] / c["U"]
     sims = {st: lbm.Simulation(c, storage=st) for st in ("f64", "f32", "f16")}
     try:
-        for t in (0.5, 1.0, 1.5, 2.0):
+        for t in (0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 5.0):
             r = {}
             for st, sim in sims.items():
                 sim.step(int(round(t * T)) - sim.info()["step"])
@@ -199,8 +252,8 @@ def test_batch256_full_size_sampled_instances(storage):
     """The benchmarked batch as timed: 256 static-drop / layered-channel instances, 32..512
     per axis (1.9e7 nodes, seed 1), one context, autotuned launch, 100 steps.  Eight of the
     instances (the smallest, the largest, the widest, the tallest and four drawn with a
-    fixed seed) against the oracle run of that instance alone: FP64 bitwise, FP32 to the
-    storage tolerance (phi: or 4x the oracle's own spread, for a drop centred on a node)."""
+    fixed seed) against the oracle run of that instance alone: FP64 bitwise, FP32 phi, u and
+    p to the storage tolerance (a drop centred on a node: see check_reduced)."""
     batch = cases.batch_ensemble(256, seed=1)
     nodes = [c["nx"] * c["ny"] for c in batch]
     pick = {int(np.argmin(nodes)), int(np.argmax(nodes)),
@@ -216,24 +269,21 @@ def test_batch256_full_size_sampled_instances(storage):
     print("[batch256 %s] %d nodes, launch %s" % (storage, sum(nodes), info), flush=True)
     for k in sorted(pick):
         c = batch[k]
-        e = errors(c, got[k], run_oracle(c, steps))
-        report("batch256 inst %d %dx%d %s" % (k, c["nx"], c["ny"], c["name"]), storage, e)
+        name = "batch256 inst %d %dx%d %s" % (k, c["nx"], c["ny"], c["name"])
+        ref = run_oracle(c, steps)
         if storage == "f64":
+            e = errors(c, got[k], ref)
+            report(name, storage, e)
             assert max(e.values()) <= TOL["f64"]
             continue
-        assert e["u"] <= TOL["f32"]
-        bound = TOL["f32"]
-        if e["phi"] > bound:
-            bound = max(bound, 4.0 * sensitivity(c, steps)["phi"])
-        assert e["phi"] <= bound
+        check_reduced(name, c, got[k], ref, steps, storage, ("phi", "u", "p"))
 
 
 def test_impact_re500_wall_top_stays_finite():
     """The same Re = 500 set-up (1500 x 500, R = 100, H_w = 50) with a bounce-back wall in
     place of the open top: the bulk update stays finite to t* = 4 (16,000 steps) in every
-    format, sum(phi) holds to round-off, and the FP32 and FP16 spreading radii track the
-    FP64 format's.  With the open top the run fails once the splash reaches that side
-    (t* ~ 2.1-2.4); the wall isolates that failure to the open-side rule."""
+    format, sum(phi) holds to round-off (nothing leaves a closed box), and the FP32 and FP16
+    spreading radii track the FP64 format's."""
     c = cases.droplet_impact(1500, 500, D=200, Re=500, film=0.25)
     c["bc_yhi"] = cases.WALL
     T = c["D"] / c["U"]

@@ -1,15 +1,20 @@
 """GPU parity of the HIP library against the FP64 CPU oracle, on the same seeded inputs.
 
 Tolerances (max norm, normalised as in tests/parity.py): FP64 storage 1e-12 on phi, u, p;
-FP32 storage 1e-5 on phi and u; FP16-deviation storage 1e-3 on u.  Chaotic runs
-(spinodal) are compared field by field only over short horizons.
+FP32 storage 1e-5 on phi, u and p; FP16-deviation storage 1e-3 on u and phi, and 1e-2 on
+p (ten times the velocity tolerance: p sums eight stored 16-bit deviations and the
+rounding of each is relative to the deviation, not to p).  Where the tolerance cannot
+apply -- chaotic runs (spinodal, high-Re impact) beyond a few steps, and the nodes around
+a drop centre that falls on a node -- the bar is a stated bound on the oracle's own
+conditioning, or statistics, as each test says.
 """
 import numpy as np
 import pytest
 
 from oracle import diag
 from paper_1710_09541_amd import cases, lbm
-from tests.parity import TOL, errors, perturbed, report, run_hip, run_oracle, sensitivity
+from tests.parity import (TOL, check_reduced, errors, perturbed, report, run_hip, run_oracle,
+                          sensitivity)
 
 pytestmark = pytest.mark.gpu
 
@@ -32,16 +37,22 @@ def test_static_drop_f64_2000_steps():
     _check("static_drop 64^2", cases.static_drop(), 2000, "f64")
 
 
-@pytest.mark.parametrize("storage,fields", [("f32", ("phi", "u")), ("f16", ("u",))])
+@pytest.mark.parametrize("storage,fields", [("f32", ("phi", "u", "p")), ("f16", ("u", "phi"))])
 def test_static_drop_reduced_storage_1000_steps(storage, fields):
-    _check("static_drop 64^2", cases.static_drop(), 1000, storage, fields)
+    e = _check("static_drop 64^2", cases.static_drop(), 1000, storage, fields)
+    if storage == "f16":
+        assert e["p"] <= 1e-2, e["p"]
 
 
 @pytest.mark.parametrize("storage,steps,fields", [("f64", 300, ("phi", "u", "p")),
-                                                  ("f32", 1000, ("phi", "u"))])
+                                                  ("f32", 1000, ("phi", "u", "p")),
+                                                  ("f16", 1000, ("u", "phi"))])
 def test_layered_poiseuille_16x512(storage, steps, fields):
-    """Walls in y (half-way bounce-back), step mu, ratio 1000, u_max = 1e-3."""
-    _check("poiseuille 16x512", cases.layered_poiseuille(), steps, storage, fields)
+    """Walls in y (half-way bounce-back), step mu, ratio 1000, u_max = 1e-3 (p against the
+    flow's dynamic pressure rho_l u_max^2)."""
+    e = _check("poiseuille 16x512", cases.layered_poiseuille(), steps, storage, fields)
+    if storage == "f16":
+        assert e["p"] <= 1e-2, e["p"]
 
 
 # The impact and the spinodal are ill-conditioned: the oracle itself, with phi0 perturbed
@@ -66,8 +77,8 @@ def test_f64_bitwise_equal_to_oracle(name, make, steps):
     assert ndiff == 0
 
 @pytest.mark.parametrize("storage,steps,fields", [("f64", 40, ("phi", "u", "p")),
-                                                  ("f32", 10, ("phi", "u")),
-                                                  ("f16", 10, ("u",))])
+                                                  ("f32", 10, ("phi", "u", "p")),
+                                                  ("f16", 10, ("u", "phi"))])
 def test_droplet_impact_512x128(storage, steps, fields):
     """The impact at the oracle's size (D = 64): bounce-back floor, open top, Re = 100."""
     _check("impact 512x128 Re100", cases.droplet_impact(512, 128, D=64, Re=100), steps, storage,
@@ -77,7 +88,7 @@ def test_droplet_impact_512x128(storage, steps, fields):
 def test_droplet_impact_full_size_f32():
     """2048 x 512, D = 256, Re = 100, in the autotuned launch configuration, 10 steps."""
     _check("impact 2048x512 Re100", cases.droplet_impact(2048, 512, D=256, Re=100), 10, "f32",
-           ("phi", "u"), kernel="auto")
+           ("phi", "u", "p"), kernel="auto")
 
 
 def test_spinodal_full_size_f64_autotuned():
@@ -89,32 +100,44 @@ def test_spinodal_full_size_f64_autotuned():
 @pytest.mark.parametrize("storage,steps", [("f32", 2), ("f32", 50), ("f16", 2), ("f16", 50)])
 def test_spinodal_full_size_reduced_vs_oracle(storage, steps):
     """The benchmarked workload itself: 1024 x 1024 spinodal in the launch configuration
-    the benchmark times (autotuned kernel, tile height and stores, graph replay), every node
-    against the oracle.  The random initial field has nodes of nearly vanishing grad phi,
-    where the direction of n is set by rounding: the oracle itself, with phi0 perturbed by
-    relative noise of 1e-7 (FP32 rounding), moves phi by 4e-5 after one step and 1.4e-2
-    after 50.  For FP16 storage the noise is 5e-7: the size at which the oracle's u departs
-    after 2 steps as far as the FP16 format's does (1.5e-5).
-    * Whole field: each field within the storage tolerance or 4x the oracle's spread under
-      that noise, whichever is larger.
-    * After 2 steps, nodes where the noise is not amplified (the perturbed oracle moves phi
+    the benchmark times (autotuned kernel, tile height and stores, graph replay), against
+    the oracle.  The random initial field has nodes of nearly vanishing grad phi, where the
+    direction of n is set by rounding, so the oracle itself moves when its input moves at
+    the size of a 32-bit rounding (relative noise 2^-23, FP32's unit roundoff, fixed by the
+    format): phi by 4e-5 after one step and 1.4e-2 after 50.
+    * FP32, every node: each field within the storage tolerance or 4x that spread of the
+      oracle, whichever is larger (a conditioning bound, not a tolerance).
+    * After 2 steps, nodes where that noise is not amplified (the perturbed oracle moves phi
       and u by less than 10x the noise), less a margin of `steps` + 2 nodes around the
-      amplified ones (about 8 % of the grid): phi and u within the storage tolerance (u only
-      for FP16).  By 50 steps the amplified regions cover the grid."""
-    eps = {"f32": 1e-7, "f16": 5e-7}[storage]
+      amplified ones (about 8 % of the grid): phi and u within the storage tolerance (FP32)
+      and u (FP16).  FP16 after 2 steps: u within its tolerance on every node as well.
+    * FP16 after 50 steps, where the spread exceeds its tolerance: statistics only, the
+      coarsening length L = 2 N / crossings within 2 % and sum(phi) within 1e-4 of the
+      oracle's."""
+    eps = 2.0 ** -23
     c = cases.spinodal(1024, seed=0)
     ref = run_oracle(c, steps)
     got = run_hip(c, steps, storage, kernel="auto", stores="auto", use_graph=True)
     e = errors(c, got, ref)
     report("spinodal 1024^2 %d steps" % steps, storage, e)
+    if storage == "f16" and steps > 2:
+        L_gpu, L_ref = _crossing_length(got["phi"]), _crossing_length(ref["phi"])
+        dsum = abs(float(got["phi"].sum()) / float(ref["phi"].sum()) - 1)
+        print("[statistics] spinodal 1024^2 %d steps f16: L %.4f vs oracle %.4f, sum phi %.1e"
+              % (steps, L_gpu, L_ref, dsum), flush=True)
+        assert abs(L_gpu / L_ref - 1) < 0.02
+        assert dsum < 1e-4
+        return
     pert = perturbed(c, steps, eps=eps)
-    sens = errors(c, pert, ref)
-    fields = ("phi", "u", "p") if storage == "f32" else ("u",)
-    for f in fields:
-        bound = max(TOL[storage], 4 * sens[f])
-        print("[parity]   %s: error %.2e, oracle spread %.2e, bound %.2e" % (f, e[f], sens[f], bound),
-              flush=True)
-        assert e[f] <= bound, (storage, steps, f, e[f], bound)
+    if storage == "f32":
+        sens = errors(c, pert, ref)
+        for f in ("phi", "u", "p"):
+            bound = max(TOL[storage], 4 * sens[f])
+            print("[parity]   %s: error %.2e, oracle spread %.2e, bound %.2e"
+                  % (f, e[f], sens[f], bound), flush=True)
+            assert e[f] <= bound, (storage, steps, f, e[f], bound)
+    else:
+        assert e["u"] <= TOL[storage], e["u"]
     if steps > 2:
         return
     u_ref = np.sqrt(ref["ux"] ** 2 + ref["uy"] ** 2)
@@ -139,6 +162,12 @@ def test_spinodal_full_size_reduced_vs_oracle(storage, steps):
     if storage == "f32":
         assert e_phi <= TOL[storage], e_phi
     assert e_u <= TOL[storage], e_u
+
+
+def _crossing_length(phi):
+    s = phi >= 0.5
+    cr = np.count_nonzero(s != np.roll(s, 1, axis=1)) + np.count_nonzero(s != np.roll(s, 1, axis=0))
+    return 2.0 * phi.size / max(cr, 1)
 
 
 def test_spinodal_4096_f64_bitwise_and_f32_within_spread():
@@ -375,21 +404,16 @@ def test_batch_equals_solo():
 
 
 def test_batch_against_oracle():
+    """Six instances of uneven size in one context, FP32, 200 steps: u, phi and p of each
+    against its own oracle run (a drop centred on a node: see check_reduced)."""
     batch = cases.batch_ensemble(n=6, seed=1, lo=32, hi=96)
     with lbm.Simulation(batch, storage="f32") as sim:
         sim.step(200)
         got = [sim.moments(k) for k in range(len(batch))]
     for k, c in enumerate(batch):
-        e = errors(c, got[k], run_oracle(c, 200))
-        report("batch inst %d %dx%d" % (k, c["nx"], c["ny"]), "f32", e)
-        assert e["u"] <= TOL["f32"]
-        # phi: the tolerance, or (for a drop whose centre sits on a node, where the normal
-        # direction is decided by rounding) a few times the oracle's own spread under
-        # 32-bit-sized perturbations of its input, whichever is larger
-        bound = TOL["f32"]
-        if e["phi"] > bound:
-            bound = max(bound, 4.0 * sensitivity(c, 200)["phi"])
-        assert e["phi"] <= bound
+        fields = ("phi", "u", "p") if c["name"] == "static_drop" else ("phi", "u")
+        check_reduced("batch inst %d %dx%d" % (k, c["nx"], c["ny"]), c, got[k],
+                      run_oracle(c, 200), 200, "f32", fields)
 
 
 def test_checkpoint_resume_bitwise():
