@@ -220,6 +220,20 @@ int lbm_moments_device(lbm_ctx* c, int32_t inst, double* d_out5);
  * LBM_ERR_DEVICE on a HIP error.  Synchronises. */
 int lbm_reduce(lbm_ctx* c, int32_t inst, const double* mask, lbm_diag* out);
 
+/* lbm_reduce for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same diagnostics, bit for bit,
+ * from the same kernels, but the moment planes, partials and result go to a fixed device
+ * scratch array the library holds on each GPU from its load until the process ends
+ * (42 MB: five FP64 planes of at most 1,048,576 nodes, plus 13,312 partials).  The call
+ * itself allocates nothing: no hipMalloc, hipFree or allocating library routine (the
+ * scratch address is looked up once per GPU at lbm_init, and the pinned host result buffer
+ * is the context's own from lbm_init).  LBM_ERR_RANGE for an instance of more than
+ * 1,048,576 nodes (nothing is computed), otherwise as lbm_reduce.  Every context on one GPU
+ * shares that GPU's scratch, which keeps the last call's contents: calls that overlap in
+ * time on one GPU (other threads, other streams) race and must be serialised by the
+ * caller.  Synchronises the context's stream. */
+int lbm_reduce_noalloc(lbm_ctx* c, int32_t inst, const double* mask, lbm_diag* out);
+
 /* Serialises the complete state (distributions, phi u of the previous step, step count).
  * With buf == NULL only *bytes is set to the size needed.  Synchronises. */
 int lbm_get_state(lbm_ctx* c, void* buf, size_t* bytes);

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -43,6 +44,21 @@ constexpr int NSTRIP = 3;
 constexpr int STRIP_TILES[NSTRIP] = {0, 8, 16};
 constexpr int GRAPH_STEPS[NGRAPH] = {2, 16, 64};
 constexpr int PLANE_PAD = 192;  // elements added to each plane: breaks power-of-two plane strides
+
+// Device scratch of lbm_reduce_noalloc, for callers that cannot allocate: the five FP64
+// moment planes of one instance of at most NOALLOC_MAX_NODES nodes, then the reduction's
+// per-block partials and its result.  Every GPU the library runs on holds one copy, from the
+// library's load until the process ends; all contexts on that GPU share it.  Host code uses
+// the address hipGetSymbolAddress returned for the device (noalloc_scratch_of), never the
+// array's name, which on the host is only a stand-in.
+constexpr int64_t NOALLOC_MAX_NODES = 1 << 20;
+constexpr int64_t NOALLOC_PARTIALS = (int64_t)REDUCE_MAX_BLOCKS * REDUCE_SLOTS;
+constexpr int64_t NOALLOC_DOUBLES = 5 * NOALLOC_MAX_NODES + NOALLOC_PARTIALS + 16;
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
 
 struct Instance {
     lbm_params p;
@@ -109,6 +125,8 @@ struct lbm_ctx {
     bool nt_store = false;     // non-temporal population stores
     bool persistent = false;   // persistent grid of resident blocks
     int num_cu = 0;            // compute units of the device
+    int device = 0;            // the device current at lbm_init
+    double* noalloc = nullptr; // that device's scratch of lbm_reduce_noalloc
     int persist_override = 0;  // LBM_PERSIST_BLOCKS: blocks per XCD of a persistent grid
     // resident blocks per CU, by tile rows and store policy (-1: not asked yet)
     mutable int per_cu[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};
@@ -429,6 +447,26 @@ int reduce_inst(lbm_ctx* c, int inst, const double* mask, double* res /*12*/) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     memcpy(res, c->h_red, 12 * sizeof(double));
     return LBM_OK;
+}
+
+// The device address of `scratch` on device dev (current), taken once per device with
+// hipGetSymbolAddress; nullptr (and the message in c) on failure.
+double* noalloc_scratch_of(lbm_ctx* c, int dev) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        fail(c, LBM_ERR_DEVICE, "device index beyond the no-allocation scratch table");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            hip_fail(c, e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+            return nullptr;
+        }
+        g_noalloc_ptr[dev] = (double*)ptr;
+    }
+    return g_noalloc_ptr[dev];
 }
 
 int check_finite(lbm_ctx* c) {
@@ -881,6 +919,10 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
             hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, dev) !=
                 hipSuccess)
             c->num_cu = 0;
+        c->device = dev;
+        // the no-allocation scratch of this device, looked up once per device at set-up
+        c->noalloc = noalloc_scratch_of(c, dev);
+        if (!c->noalloc) return bail(LBM_ERR_DEVICE);
         const char* pb = getenv("LBM_PERSIST_BLOCKS");
         if (pb && *pb) c->persist_override = std::max(0, atoi(pb));
     }
@@ -968,6 +1010,51 @@ int lbm_reduce(lbm_ctx* c, int32_t inst, const double* mask, lbm_diag* out) {
     double r[12];
     int rc = reduce_inst(c, inst, mask, r);
     if (rc) return rc;
+    out->sum_phi = r[0];
+    out->sum_rho = r[1];
+    out->kinetic = r[2];
+    out->max_u = r[3];
+    out->min_rho = r[4];
+    out->min_phi = r[5];
+    out->max_phi = r[6];
+    out->p_in = r[7];
+    out->p_out = r[8];
+    out->interface_crossings = r[9];
+    out->spread_radius = r[10];
+    out->nonfinite = (int64_t)r[11];
+    out->step = c->step;
+    return LBM_OK;
+}
+
+int lbm_reduce_noalloc(lbm_ctx* c, int32_t inst, const double* mask, lbm_diag* out) {
+    if (!c) return fail(nullptr, LBM_ERR_PARAM, "context is NULL");
+    if (!out) return fail(c, LBM_ERR_PARAM, "output is NULL");
+    if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, LBM_ERR_RANGE, "no such instance");
+    const Instance& I = c->inst[inst];
+    if (I.n_nodes > NOALLOC_MAX_NODES) {
+        char b[200];
+        snprintf(b, sizeof b, "lbm_reduce_noalloc: instance %d has %lld nodes, more than the "
+                 "%lld its fixed device scratch holds; use lbm_reduce", (int)inst,
+                 (long long)I.n_nodes, (long long)NOALLOC_MAX_NODES);
+        return fail(c, LBM_ERR_RANGE, b);
+    }
+    if (!c->noalloc) return fail(c, LBM_ERR_DEVICE, "no-allocation scratch unavailable");
+    // the moment planes, the partials and the result, all in the device's fixed scratch;
+    // every slot read is written first by this call's kernels, so nothing needs clearing
+    double* mom = c->noalloc;
+    double* partials = mom + 5 * NOALLOC_MAX_NODES;
+    double* res = partials + NOALLOC_PARTIALS;
+    int rc = moments_to(c, inst, mom);
+    if (rc) return rc;
+    double m[5] = {0, 0, 0, 0, -1};
+    if (mask) memcpy(m, mask, sizeof m);
+    hipError_t e = launch_reduce(mom, I.p.nx, I.p.ny, I.p.bc_ylo == LBM_BC_PERIODIC, m, partials,
+                                 res, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "reduce launch");
+    HIPCHK(c, hipMemcpyAsync(c->h_red, res, 12 * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const double* r = c->h_red;
     out->sum_phi = r[0];
     out->sum_rho = r[1];
     out->kinetic = r[2];

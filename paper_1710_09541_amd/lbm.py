@@ -26,8 +26,8 @@ STORAGE = {"f64": LBM_STORE_F64, "f32": LBM_STORE_F32, "f16": LBM_STORE_F16}
 KERNEL = {"auto": LBM_KERNEL_AUTO, "fused": LBM_KERNEL_FUSED, "split": LBM_KERNEL_SPLIT}
 
 EXPORTS = ("lbm_init", "lbm_step", "lbm_moments", "lbm_moments_device", "lbm_reduce",
-           "lbm_get_state", "lbm_set_state", "lbm_info", "lbm_build_id", "lbm_last_error",
-           "lbm_destroy")
+           "lbm_reduce_noalloc", "lbm_get_state", "lbm_set_state", "lbm_info", "lbm_build_id",
+           "lbm_last_error", "lbm_destroy")
 
 
 class lbm_params(C.Structure):
@@ -87,6 +87,7 @@ def load():
     L.lbm_moments.argtypes = [C.c_void_p, C.c_int32, D, D, D, D, D]
     L.lbm_moments_device.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
     L.lbm_reduce.argtypes = [C.c_void_p, C.c_int32, D, P(lbm_diag)]
+    L.lbm_reduce_noalloc.argtypes = [C.c_void_p, C.c_int32, D, P(lbm_diag)]
     L.lbm_get_state.argtypes = [C.c_void_p, C.c_void_p, P(C.c_size_t)]
     L.lbm_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
     L.lbm_info.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_int32), P(C.c_int32),
@@ -195,7 +196,7 @@ def lbm_moments_device(ctx, inst, d_ptr):
     _check(load().lbm_moments_device(ctx, int(inst), C.c_void_p(d_ptr)), ctx)
 
 
-def lbm_reduce(ctx, inst, mask=None):
+def _reduce(fn, ctx, inst, mask):
     d = lbm_diag()
     m = None
     if mask is not None:
@@ -203,8 +204,17 @@ def lbm_reduce(ctx, inst, mask=None):
         if m_arr.size != 5:
             raise ValueError("mask is (xc, yc, r_in, r_out, y_row): 5 values")
         m = _dptr(m_arr)
-    _check(load().lbm_reduce(ctx, int(inst), m, C.byref(d)), ctx)
+    _check(fn(ctx, int(inst), m, C.byref(d)), ctx)
     return {k: getattr(d, k) for k, _ in lbm_diag._fields_}
+
+
+def lbm_reduce(ctx, inst, mask=None):
+    return _reduce(load().lbm_reduce, ctx, inst, mask)
+
+
+def lbm_reduce_noalloc(ctx, inst, mask=None):
+    """lbm_reduce through the library's fixed device scratch (no allocation in the call)."""
+    return _reduce(load().lbm_reduce_noalloc, ctx, inst, mask)
 
 
 def lbm_get_state(ctx) -> bytes:
