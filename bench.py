@@ -177,6 +177,7 @@ def measure(cs, storage, steps, warmup, kernel="auto", tile_rows=0, final_stats=
             "kernel": info["kernel"], "tile_rows": info["tile_rows"], "stores": info["stores"],
             "grid": info["grid"], "tile_order": ("rows" if info["strip"] == "rows"
                                                  else "strips of %d tiles" % info["strip"]),
+            "narrow_tiles": info["narrow"],
             "f_lattice": qf,
             "alg_bytes_per_lu": alg_bytes(storage, qf), "achieved_gbs": ach,
             "frac_hbm_peak": ach / PEAK_HBM_GBS, "nodes": nodes, "steps": steps,
@@ -195,7 +196,8 @@ def host_round_trip(cs, storage, steps, r):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim = lbm.Simulation(cs, storage=storage, kernel=r["kernel"], tile_rows=r["tile_rows"],
-                         stores=r["stores"], grid=r["grid"], strip=strip)
+                         stores=r["stores"], grid=r["grid"], strip=strip,
+                         narrow=r["narrow_tiles"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sim.step(steps)
@@ -330,7 +332,8 @@ def batch_accuracy(cs, storage, steps, refs, r, masks):
     worst = {"phi": 0.0, "u": 0.0, "p": 0.0}
     judged = {"phi": 0.0, "u": 0.0, "p": 0.0}
     with lbm.Simulation(cs, storage=storage, kernel=r["kernel"], tile_rows=r["tile_rows"],
-                        stores=r["stores"], grid=r["grid"], strip=strip) as sim:
+                        stores=r["stores"], grid=r["grid"], strip=strip,
+                        narrow=r["narrow_tiles"]) as sim:
         sim.step(steps)
         for k, ref in refs.items():
             got = sim.moments(k)
@@ -506,7 +509,8 @@ def main():
         "config": {"workload": desc, "storage": args.storage, "instances": len(cs),
                    "nodes": nodes, "kernel": kname, "tile_rows": main_r["tile_rows"],
                    "stores": main_r["stores"], "grid": main_r["grid"],
-                   "tile_order": main_r["tile_order"]},
+                   "tile_order": main_r["tile_order"],
+                   "narrow_tiles": main_r["narrow_tiles"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),

@@ -107,6 +107,13 @@ enum { LBM_GRID_AUTO = 0, LBM_GRID_TILES = 1, LBM_GRID_PERSISTENT = 2 };
  * than the caches; whole rows win where it fits.  Results are bitwise identical. */
 enum { LBM_STRIP_AUTO = 0, LBM_STRIP_ROWS = -1 };   /* or a strip width of 8 or 16 tiles */
 
+/* Tiles at the right end of an instance whose width is not a multiple of 64.  Tiles are 64
+ * nodes wide; with narrow tiles ON, the last nx mod 64 = r columns (r <= 48) are covered by
+ * 32- and/or 16-wide tiles, 2 or 4 times as tall, so fewer of the block's threads hold no
+ * node (the step's time follows the threads launched, not the nodes).  AUTO lets the
+ * autotuner time both where they differ.  Results are bitwise identical either way. */
+enum { LBM_NARROW_AUTO = 0, LBM_NARROW_OFF = -1, LBM_NARROW_ON = 1 };
+
 /* kernel choice for the step */
 enum {
     LBM_KERNEL_AUTO = 0,  /* the autotuner picks */
@@ -153,6 +160,7 @@ typedef struct {
                                  grid sizes) */
     int32_t grid;             /* LBM_GRID_* (AUTO: one block per tile) */
     int32_t strip;            /* LBM_STRIP_AUTO (timed at lbm_init), LBM_STRIP_ROWS, 8 or 16 */
+    int32_t narrow_tiles;     /* LBM_NARROW_AUTO (timed at lbm_init), LBM_NARROW_OFF or _ON */
 } lbm_options;
 
 /* Integral diagnostics of one instance, FP64 accumulation in a fixed order, over the
@@ -246,11 +254,11 @@ int lbm_get_state(lbm_ctx* c, void* buf, size_t* bytes);
 int lbm_set_state(lbm_ctx* c, const void* buf, size_t bytes);
 
 /* Number of steps taken; the kernel (LBM_KERNEL_FUSED / SPLIT), tile rows, population
- * stores (LBM_STORES_CACHED / STREAMING), launch grid (LBM_GRID_TILES / PERSISTENT) and tile
- * order (LBM_STRIP_ROWS, 8 or 16) the context runs with.  Any pointer may be NULL;
- * LBM_ERR_PARAM if c is NULL. */
+ * stores (LBM_STORES_CACHED / STREAMING), launch grid (LBM_GRID_TILES / PERSISTENT), tile
+ * order (LBM_STRIP_ROWS, 8 or 16) and narrow tiles (LBM_NARROW_ON / OFF) the context runs
+ * with.  Any pointer may be NULL; LBM_ERR_PARAM if c is NULL. */
 int lbm_info(const lbm_ctx* c, int64_t* step, int32_t* kernel, int32_t* tile_rows,
-             int32_t* stores, int32_t* grid, int32_t* strip);
+             int32_t* stores, int32_t* grid, int32_t* strip, int32_t* narrow_tiles);
 
 /* Build provenance: the sha256 (64 hex digits) of the source files the library was built
  * from, fixed at compile time; the Python binding compares it with the sources beside the

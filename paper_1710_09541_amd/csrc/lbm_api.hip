@@ -103,8 +103,11 @@ struct lbm_ctx {
     void* phiplane = nullptr;
     void* rplane[2] = {nullptr, nullptr};  // that state, written with buffer i
     InstDev* d_insts = nullptr;
-    TileList lists[3][NSTRIP];  // by tile height (4, 8, 16 rows) and tile order
+    // by tile height (4, 8, 16 rows), tile order and whether the last columns of an instance
+    // whose width is not a multiple of 64 take narrower tiles
+    TileList lists[3][NSTRIP][2];
     int strip = 0;             // tile order in use (index into STRIP_TILES)
+    int narrow = 0;            // 1: narrow tiles at the right end of ragged instances
     double* mom = nullptr;     // 5 * max nodes, moments scratch
     double* partials = nullptr;
     double* red_out = nullptr;
@@ -254,19 +257,53 @@ void fill_inst(Instance& I, int storage, const double* phi0, const double* ux0, 
     I.n_nodes = n;
 }
 
+// Narrow tiles for the last r = nx mod 64 columns of an instance (narrow = true): 16 wide
+// for r <= 16, 32 wide for r <= 32, 32 + 16 wide for r <= 48; a 64-wide column otherwise.
+// A narrow tile keeps the block's 256 threads busy with 2 or 4 rows per wavefront where a
+// 64-wide one would leave 64 - r lanes of every row without a node.  Every column of tiles
+// is appended to cols as (x0, width class).
+void narrow_columns(int nx, bool narrow, std::vector<std::pair<int, int>>& cols) {
+    const int full = nx / TILE_X * TILE_X, r = nx - full;
+    for (int x0 = 0; x0 < full; x0 += TILE_X) cols.push_back({x0, 0});
+    if (r == 0) return;
+    if (!narrow || r > 48) {
+        cols.push_back({full, 0});
+    } else if (r <= 16) {
+        cols.push_back({full, 2});
+    } else {
+        cols.push_back({full, 1});
+        if (r > 32) cols.push_back({full + 32, 2});
+    }
+}
+
 // the tiles of every instance in turn; within an instance, row after row (strip_tiles = 0)
-// or strip after strip of strip_tiles tiles, row after row inside each strip
-std::vector<TileDesc> build_tiles(const std::vector<Instance>& v, int rows, int strip_tiles) {
+// or strip after strip of strip_tiles tiles, row after row inside each strip.  A tile of
+// width class w is rows << w rows tall; it is listed in the row of tiles where it starts.
+std::vector<TileDesc> build_tiles(const std::vector<Instance>& v, int rows, int strip_tiles,
+                                  bool narrow) {
     std::vector<TileDesc> t;
     for (size_t k = 0; k < v.size(); ++k) {
         const int nx = v[k].p.nx;
+        std::vector<std::pair<int, int>> cols;
+        narrow_columns(nx, narrow, cols);
         const int sw = (strip_tiles > 0 && strip_tiles * TILE_X < nx) ? strip_tiles * TILE_X : nx;
         for (int xs = 0; xs < nx; xs += sw)
             for (int y0 = 0; y0 < v[k].p.ny; y0 += rows)
-                for (int x0 = xs; x0 < std::min(nx, xs + sw); x0 += TILE_X)
-                    t.push_back({(int32_t)k, x0, y0, 0});
+                for (const auto& col : cols)
+                    if (col.first >= xs && col.first < std::min(nx, xs + sw) &&
+                        y0 % (rows << col.second) == 0)
+                        t.push_back({(int32_t)k, col.first, y0, col.second});
     }
     return t;
+}
+
+// whether narrow tiles give another tiling than 64-wide ones for some instance
+bool narrow_differs(const lbm_ctx* c) {
+    for (const Instance& I : c->inst) {
+        const int r = I.p.nx % TILE_X;
+        if (r > 0 && r <= 48) return true;
+    }
+    return false;
 }
 
 // whether strips of strip_tiles tiles give another order than whole rows for some instance
@@ -315,9 +352,10 @@ void free_all(lbm_ctx* c) {
                     c->d_insts, c->mom,       c->partials, c->red_out};
     for (void* p : ptrs)
         if (p) hipFree(p);
-    for (auto& ls : c->lists)
-        for (auto& l : ls)
-            if (l.dev) hipFree(l.dev);
+    for (auto& by_rows : c->lists)
+        for (auto& by_order : by_rows)
+            for (auto& l : by_order)
+                if (l.dev) hipFree(l.dev);
     if (c->h_red) hipHostFree(c->h_red);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
@@ -342,13 +380,15 @@ int persist_blocks(const lbm_ctx* c, int rows, bool nt) {
 bool runs_persistent(const lbm_ctx* c) {
     if (!c->persistent || c->kernel != LBM_KERNEL_FUSED) return false;
     const int pb = persist_blocks(c, c->tile_rows, c->nt_store);
-    const int per = (c->lists[list_index(c->tile_rows)][0].count + NXCD - 1) / NXCD;
+    const int per = (c->lists[list_index(c->tile_rows)][c->strip][c->narrow].count + NXCD - 1) /
+                    NXCD;
     return pb > 0 && pb < per;
 }
 
-StepArgs step_args(lbm_ctx* c, int src, bool pull, int rows, bool split, void* q, int strip) {
+StepArgs step_args(lbm_ctx* c, int src, bool pull, int rows, bool split, void* q, int strip,
+                   int narrow) {
     StepArgs a;
-    const TileList& L = c->lists[list_index(rows)][strip];
+    const TileList& L = c->lists[list_index(rows)][strip][narrow];
     a.insts = c->d_insts;
     a.tiles = L.dev;
     a.ntiles = L.count;
@@ -373,11 +413,11 @@ StepArgs step_args(lbm_ctx* c, int src, bool pull, int rows, bool split, void* q
 int launch_one(lbm_ctx* c, hipStream_t st) {
     StepArgs a;
     if (c->streamed)
-        a = step_args(c, c->cur, false, 4, false, c->q, c->strip);
+        a = step_args(c, c->cur, false, 4, false, c->q, c->strip, c->narrow);
     else
     {
         a = step_args(c, c->cur, true, c->tile_rows, c->kernel == LBM_KERNEL_SPLIT, c->q,
-                      c->strip);
+                      c->strip, c->narrow);
         a.nt_store = c->nt_store;
         a.persist = runs_persistent(c) ? persist_blocks(c, c->tile_rows, c->nt_store) : 0;
     }
@@ -425,8 +465,8 @@ int capture_steps(lbm_ctx* c, int g, int from) {
 int moments_to(lbm_ctx* c, int inst, double* out) {
     const Instance& I = c->inst[inst];
     // whole-row order: an instance's tiles are one contiguous run of the 4-row list
-    StepArgs a = step_args(c, c->cur, !c->streamed, 4, false, c->q, 0);
-    a.tiles = c->lists[0][0].dev + I.tile_begin_k1;
+    StepArgs a = step_args(c, c->cur, !c->streamed, 4, false, c->q, 0, 0);
+    a.tiles = c->lists[0][0][0].dev + I.tile_begin_k1;
     a.ntiles = I.tile_count_k1;
     hipError_t e = launch_moments(c->storage, a, out);
     if (e != hipSuccess) return hip_fail(c, e, "moments launch");
@@ -487,8 +527,9 @@ int check_finite(lbm_ctx* c) {
 // ------------------------------------------------------------------ autotuner cache
 // If the environment variable LBM_AUTOTUNE_CACHE names a file, tuned choices are kept there,
 // one text line per configuration:
-//   lbm-tune-v3 <key> <kernel> <tile_rows> <streaming stores 0/1> <persistent grid 0/1>
+//   lbm-tune-v4 <key> <kernel> <tile_rows> <streaming stores 0/1> <persistent grid 0/1>
 //               <tile order 0/1/2: whole rows, strips of 8, strips of 16 tiles>
+//               <narrow tiles at the right end of ragged instances 0/1>
 // The key covers everything the timing depends on: the GPU architecture, storage, phase-
 // field lattice, the requested kernel / tile rows / store policy / grid / order, the number of
 // instances and every instance's grid size.  A missing, unreadable or malformed file only means the
@@ -504,7 +545,7 @@ std::string tune_key(const lbm_ctx* c) {
         if (ch == ' ') ch = '_';
     k << arch << ":s" << c->storage << ":q" << c->qf << ":k" << c->opt.kernel << ":r"
       << c->opt.tile_rows << ":w" << c->opt.stores << ":g" << c->opt.grid << ":o" << c->opt.strip
-      << ":n" << c->inst.size();
+      << ":t" << c->opt.narrow_tiles << ":n" << c->inst.size();
     for (const Instance& I : c->inst) k << ":" << I.p.nx << "x" << I.p.ny;
     return k.str();
 }
@@ -518,14 +559,16 @@ bool tune_cache_lookup(lbm_ctx* c, const std::string& key) {
     while (std::getline(in, line)) {
         std::istringstream ls(line);
         std::string tag, k;
-        int kernel = 0, rows = 0, nt = 0, pg = 0, si = 0;
-        if (!(ls >> tag >> k >> kernel >> rows >> nt >> pg >> si) || tag != "lbm-tune-v3" ||
-            k != key)
+        int kernel = 0, rows = 0, nt = 0, pg = 0, si = 0, nw = 0;
+        if (!(ls >> tag >> k >> kernel >> rows >> nt >> pg >> si >> nw) ||
+            tag != "lbm-tune-v4" || k != key)
             continue;
         if ((kernel != LBM_KERNEL_FUSED && kernel != LBM_KERNEL_SPLIT) || list_index(rows) < 0 ||
-            (nt != 0 && nt != 1) || (pg != 0 && pg != 1) || si < 0 || si >= NSTRIP)
+            (nt != 0 && nt != 1) || (pg != 0 && pg != 1) || si < 0 || si >= NSTRIP ||
+            (nw != 0 && nw != 1))
             continue;
         c->strip = si;
+        c->narrow = nw;
         c->kernel = kernel;   // the last valid line for the key wins
         c->tile_rows = rows;
         c->nt_store = nt == 1;
@@ -539,9 +582,9 @@ void tune_cache_store(const lbm_ctx* c, const std::string& key) {
     const char* path = getenv("LBM_AUTOTUNE_CACHE");
     if (!path || !*path) return;
     std::ofstream out(path, std::ios::app);
-    if (out) out << "lbm-tune-v3 " << key << " " << c->kernel << " " << c->tile_rows << " "
+    if (out) out << "lbm-tune-v4 " << key << " " << c->kernel << " " << c->tile_rows << " "
                  << (c->nt_store ? 1 : 0) << " " << (c->persistent ? 1 : 0) << " " << c->strip
-                 << "\n";
+                 << " " << c->narrow << "\n";
 }
 
 // ------------------------------------------------------------------ autotuner
@@ -558,7 +601,7 @@ int autotune(lbm_ctx* c) {
     struct Cand {
         int kernel, rows;
         bool nt, persistent;
-        int strip;
+        int strip, narrow;
     };
     std::vector<Cand> cands;
     const bool want_fused = c->opt.kernel != LBM_KERNEL_SPLIT;
@@ -584,6 +627,15 @@ int autotune(lbm_ctx* c) {
         for (int si = 1; si < NSTRIP; ++si)
             if (strip_differs(c, STRIP_TILES[si])) strips.push_back(si);
     }
+    // narrow tiles at the right end of ragged instances: the requested choice, or both
+    // (narrow first: fewer idle lanes) where they change the tiling
+    std::vector<int> narrows;
+    if (c->opt.narrow_tiles != LBM_NARROW_AUTO)
+        narrows.push_back(c->narrow);
+    else if (narrow_differs(c))
+        narrows = {1, 0};
+    else
+        narrows.push_back(0);
     const int rows_opts[3] = {4, 8, 16};
     for (int r : rows_opts) {
         if (c->opt.tile_rows && c->opt.tile_rows != r) continue;
@@ -593,12 +645,14 @@ int autotune(lbm_ctx* c) {
             if ((nt && !want_nt) || (!nt && !want_cached)) continue;
             for (int pg = 0; pg < 2; ++pg) {
                 if ((pg && !want_persistent) || (!pg && !want_tiles)) continue;
-                for (int si : strips) {
-                    if (want_fused) cands.push_back({LBM_KERNEL_FUSED, r, nt == 1, pg == 1, si});
-                    // the split kernel runs one block per tile
-                    if (want_split && !pg)
-                        cands.push_back({LBM_KERNEL_SPLIT, r, nt == 1, false, si});
-                }
+                for (int si : strips)
+                    for (int nw : narrows) {
+                        if (want_fused)
+                            cands.push_back({LBM_KERNEL_FUSED, r, nt == 1, pg == 1, si, nw});
+                        // the split kernel runs one block per tile
+                        if (want_split && !pg)
+                            cands.push_back({LBM_KERNEL_SPLIT, r, nt == 1, false, si, nw});
+                    }
             }
         }
     }
@@ -608,6 +662,7 @@ int autotune(lbm_ctx* c) {
         c->nt_store = cands[0].nt;
         c->persistent = cands[0].persistent;
         c->strip = cands[0].strip;
+        c->narrow = cands[0].narrow;
         return LBM_OK;
     }
     HIPCHK(c, copy_n_async(c->q_tune, c->q, c->q_elems * sizeof(double), c->stream));
@@ -653,7 +708,7 @@ int autotune(lbm_ctx* c) {
     int rc = LBM_OK;
     auto args_of = [&](const Cand& cd, StepArgs& a, StepArgs& b) {
         a = step_args(c, c->cur, true, cd.rows, cd.kernel == LBM_KERNEL_SPLIT, c->q_tune,
-                      cd.strip);
+                      cd.strip, cd.narrow);
         a.nt_store = cd.nt;
         a.persist = cd.persistent ? persist_blocks(c, cd.rows, cd.nt) : 0;
         b = a;
@@ -707,6 +762,7 @@ int autotune(lbm_ctx* c) {
                 c->nt_store = cands[ci].nt;
                 c->persistent = cands[ci].persistent;
                 c->strip = cands[ci].strip;
+                c->narrow = cands[ci].narrow;
             }
         }
     }
@@ -744,6 +800,9 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
     if (o.grid < 0 || o.grid > 2) return fail(nullptr, LBM_ERR_PARAM, "unknown launch grid");
     if (o.strip != LBM_STRIP_AUTO && o.strip != LBM_STRIP_ROWS && o.strip != 8 && o.strip != 16)
         return fail(nullptr, LBM_ERR_PARAM, "strip must be 0 (auto), -1 (whole rows), 8 or 16");
+    if (o.narrow_tiles != LBM_NARROW_AUTO && o.narrow_tiles != LBM_NARROW_OFF &&
+        o.narrow_tiles != LBM_NARROW_ON)
+        return fail(nullptr, LBM_ERR_PARAM, "narrow_tiles must be 0 (auto), -1 (off) or 1 (on)");
     const auto lattice_of = [](const lbm_params& q) {
         return q.f_lattice == 0 ? (int)LBM_LATTICE_D2Q9 : (int)q.f_lattice;
     };
@@ -866,16 +925,17 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
     if (e != hipSuccess) return bail(hip_fail(c, e, "copy instances"));
     const int rows_of[3] = {4, 8, 16};
     for (int li = 0; li < 3; ++li)
-    for (int si = 0; si < NSTRIP; ++si) {
-        std::vector<TileDesc> t = build_tiles(c->inst, rows_of[li], STRIP_TILES[si]);
-        TileList& L = c->lists[li][si];
+    for (int si = 0; si < NSTRIP; ++si)
+    for (int nw = 0; nw < 2; ++nw) {
+        std::vector<TileDesc> t = build_tiles(c->inst, rows_of[li], STRIP_TILES[si], nw == 1);
+        TileList& L = c->lists[li][si][nw];
         L.rows = rows_of[li];
         L.count = (int)t.size();
         e = hipMalloc((void**)&L.dev, t.size() * sizeof(TileDesc));
         if (e != hipSuccess) return bail(hip_fail(c, e, "tile list"));
         e = hipMemcpy(L.dev, t.data(), t.size() * sizeof(TileDesc), hipMemcpyHostToDevice);
         if (e != hipSuccess) return bail(hip_fail(c, e, "tile list copy"));
-        if (li == 0 && si == 0) {
+        if (li == 0 && si == 0 && nw == 0) {
             int pos = 0;
             for (int k = 0; k < n_inst; ++k) {
                 c->inst[k].tile_begin_k1 = pos;
@@ -913,6 +973,7 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
     c->nt_store = o.stores == LBM_STORES_STREAMING;
     c->persistent = o.grid == LBM_GRID_PERSISTENT;
     c->strip = o.strip == 8 ? 1 : (o.strip == 16 ? 2 : 0);
+    c->narrow = o.narrow_tiles == LBM_NARROW_ON ? 1 : 0;
     {
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -927,7 +988,8 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
         if (pb && *pb) c->persist_override = std::max(0, atoi(pb));
     }
     if (o.kernel == LBM_KERNEL_AUTO || o.tile_rows == 0 || o.stores == LBM_STORES_AUTO ||
-        o.grid == LBM_GRID_AUTO || o.strip == LBM_STRIP_AUTO) {
+        o.grid == LBM_GRID_AUTO || o.strip == LBM_STRIP_AUTO ||
+        o.narrow_tiles == LBM_NARROW_AUTO) {
         const std::string key = tune_key(c);
         if (!tune_cache_lookup(c, key)) {
             int rc = autotune(c);
@@ -1134,7 +1196,7 @@ int lbm_set_state(lbm_ctx* c, const void* buf, size_t bytes) {
 }
 
 int lbm_info(const lbm_ctx* c, int64_t* step, int32_t* kernel, int32_t* tile_rows,
-             int32_t* stores, int32_t* grid, int32_t* strip) {
+             int32_t* stores, int32_t* grid, int32_t* strip, int32_t* narrow_tiles) {
     if (!c) return fail(nullptr, LBM_ERR_PARAM, "context is NULL");
     if (step) *step = c->step;
     if (kernel) *kernel = c->kernel;
@@ -1142,6 +1204,7 @@ int lbm_info(const lbm_ctx* c, int64_t* step, int32_t* kernel, int32_t* tile_row
     if (stores) *stores = c->nt_store ? LBM_STORES_STREAMING : LBM_STORES_CACHED;
     if (grid) *grid = runs_persistent(c) ? LBM_GRID_PERSISTENT : LBM_GRID_TILES;
     if (strip) *strip = c->strip == 0 ? LBM_STRIP_ROWS : STRIP_TILES[c->strip];
+    if (narrow_tiles) *narrow_tiles = c->narrow ? LBM_NARROW_ON : LBM_NARROW_OFF;
     return LBM_OK;
 }
 

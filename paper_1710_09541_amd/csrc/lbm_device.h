@@ -35,7 +35,9 @@ struct InstDev {
     double scale_f, inv_scale_f, scale_g, inv_scale_g;  // storage scales 2^exp
 };
 
-// One tile of TILE_X x rows nodes of one instance.
+// One tile of one instance: origin (x0, y0) and width class pad: 0 for TILE_X nodes wide
+// and 4K rows (K = rows per thread), 1 for TILE_X / 2 wide and 8K rows, 2 for TILE_X / 4 wide
+// and 16K rows (the last columns of an instance whose width is not a multiple of TILE_X).
 struct TileDesc {
     int32_t inst, x0, y0, pad;
 };

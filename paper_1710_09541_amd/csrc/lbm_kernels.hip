@@ -232,11 +232,11 @@ __device__ __forceinline__ void pull_offsets(const InstDev& I, int x, int y, int
     o[8] = bh ? 6 * plane + self : 8 * plane + src[8];
 }
 
-// The same sources as LDS indices of a (TILE_X + 4)-wide region with a two-node halo:
-// (lx, ly) is the node's unwrapped position relative to the tile origin and gy its row.
-constexpr int RW = TILE_X + 4;
-// dir[i] is the direction of the slot that was read (the opposite one after a bounce-back).
-template <bool PULL, bool INTERIOR = false>
+// The same sources as LDS indices of an RW-wide region (the tile's width + 4) with a
+// two-node halo: (lx, ly) is the node's unwrapped position relative to the tile origin and
+// gy its row.  dir[i] is the direction of the slot that was read (the opposite one after a
+// bounce-back).
+template <bool PULL, bool INTERIOR, int RW>
 __device__ __forceinline__ void pull_local(const InstDev& I, int gy, int lx, int ly, int r[9],
                                            int dir[9]) {
     const int c = (ly + 2) * RW + lx + 2;
@@ -691,7 +691,8 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
 // msrc / mdst: reduced formats, every node's (phi_w, p_w, ux_w, uy_w) as one float4, of the
 // previous step (read) and of this step (written); FP64 format, the pressure of the first
 // and the last row (two rows of doubles), which an open side needs.
-template <typename S, int K, bool PULL, int MODE, bool RING_FROM_PLANE, bool INTERIOR, int QF>
+template <typename S, int K, bool PULL, int MODE, bool RING_FROM_PLANE, bool INTERIOR, int QF,
+          int TXW>
 __device__ __forceinline__ void step_tile(
     const InstDev& I, const TileDesc& T, const S* __restrict__ fsrc,
     const S* __restrict__ gsrc, S* __restrict__ fdst, S* __restrict__ gdst,
@@ -707,15 +708,17 @@ __device__ __forceinline__ void step_tile(
         if constexpr (SCALED) return __builtin_fmaf(v, is, 0.0f);
         else return v;
     };
-    constexpr int TY = 4 * K;
-    constexpr int LW = TILE_X + 2;
+    constexpr int RPG = BLOCK / TXW;   // rows of the block's threads: 4, 8 or 16
+    constexpr int TY = RPG * K;
+    constexpr int RW = TXW + 4;        // staged region: the tile and two nodes around it
+    constexpr int LW = TXW + 2;        // phi tile: the tile and one node around it
     constexpr int NR = REF ? (TY + 4) * RW : 1;
     const int nx = I.nx, ny = I.ny, pitch = I.pitch;
-    const int w = INTERIOR ? TILE_X : min(TILE_X, nx - T.x0);
+    const int w = INTERIOR ? TXW : min(TXW, nx - T.x0);
     const int h = INTERIOR ? TY : min(TY, ny - T.y0);
     const int tid = threadIdx.x;
-    const int lx = tid & (TILE_X - 1);
-    const int ly = tid >> 6;
+    const int lx = tid & (TXW - 1);
+    const int ly = tid / TXW;
     const int x = T.x0 + lx;
 
     const S* fb = fsrc + I.off_dist;
@@ -771,7 +774,7 @@ __device__ __forceinline__ void step_tile(
     bool valid[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const int yl = ly + 4 * k;
+        const int yl = ly + RPG * k;
         valid[k] = lx < w && yl < h;
         if (valid[k]) {
             const int y = T.y0 + yl;
@@ -847,11 +850,11 @@ __device__ __forceinline__ void step_tile(
     for (int k = 0; k < K; ++k) {
         res[k] = C(0);
         if (valid[k]) {
-            const int yl = ly + 4 * k;
+            const int yl = ly + RPG * k;
             C ref[9], base = C(0);
             if (REF) {
                 int r[9], dir[9];
-                pull_local<PULL, INTERIOR>(I, T.y0 + yl, lx, yl, r, dir);
+                pull_local<PULL, INTERIOR, RW>(I, T.y0 + yl, lx, yl, r, dir);
 #pragma unroll
                 for (int i = 0; i < QF; ++i) ref[i] = sw[r[i]].x;
                 base = sw[(yl + 2) * RW + lx + 2].x;
@@ -871,7 +874,7 @@ __device__ __forceinline__ void step_tile(
                                       (yraw >= ny && I.bc_hi != BC_PERIODIC);
                 const int lyl = mirrored ? gy - T.y0 : ry;
                 int r[9], dir[9];
-                pull_local<PULL, INTERIOR>(I, gy, rx, lyl, r, dir);
+                pull_local<PULL, INTERIOR, RW>(I, gy, rx, lyl, r, dir);
 #pragma unroll
                 for (int i = 0; i < QF; ++i) ref[i] = sw[r[i]].x;
                 base = sw[(lyl + 2) * RW + rx + 2].x;
@@ -889,7 +892,7 @@ __device__ __forceinline__ void step_tile(
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if (!valid[k]) continue;
-        const int yl = ly + 4 * k;
+        const int yl = ly + RPG * k;
         const int y = T.y0 + yl;
         const C* r0 = sphi + yl * LW + lx;        // row below (y - 1)
         const C* r1 = r0 + LW;                    // own row
@@ -902,7 +905,7 @@ __device__ __forceinline__ void step_tile(
         const bool open_hi = PULL && !INTERIOR && y == ny - 1 && I.bc_hi == BC_OPEN;
         if constexpr (REF) {
             int r[9], dir[9];
-            pull_local<PULL, INTERIOR>(I, y, lx, yl, r, dir);
+            pull_local<PULL, INTERIOR, RW>(I, y, lx, yl, r, dir);
             float fd[9], eg[9], gs[9], fo[9], go[9], pw[3];
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
@@ -975,7 +978,12 @@ __device__ __forceinline__ void step_tile(
 
 
 // A tile whose staged region (two nodes around it) lies inside the grid runs a copy of the
-// body without wrap and boundary logic; edge tiles take the general path.
+// body without wrap and boundary logic; edge tiles take the general path.  Tiles are
+// TILE_X = 64 nodes wide (4K rows), except at the right end of an instance whose width is
+// not a multiple of 64, where narrower tiles cover the rest: 32 wide (8K rows) or 16 wide
+// (16K rows), width class 1 or 2 in TileDesc::pad.  The block's 256 threads then hold
+// 2 or 4 rows per wavefront instead of lanes with no node.  Every tile shape fits the LDS
+// arrays sized for the 64-wide one.
 template <typename S, int K, bool PULL, int MODE, bool RING_FROM_PLANE, int QF,
           bool PERSIST = false>
 __global__ __launch_bounds__(BLOCK) void k_step(
@@ -986,7 +994,12 @@ __global__ __launch_bounds__(BLOCK) void k_step(
     float* __restrict__ mdst, double* __restrict__ mom_out) {
     using C = typename Store<S>::C;
     constexpr int TY = 4 * K;
-    constexpr int NR = rest_deviation<S>() ? (TY + 4) * RW : 1;
+    constexpr int NR = rest_deviation<S>() ? (TY + 4) * (TILE_X + 4) : 1;
+    static_assert((8 * K + 4) * (TILE_X / 2 + 4) <= (TY + 4) * (TILE_X + 4) &&
+                  (16 * K + 4) * (TILE_X / 4 + 4) <= (TY + 4) * (TILE_X + 4) &&
+                  (8 * K + 2) * (TILE_X / 2 + 2) <= (TY + 2) * (TILE_X + 2) &&
+                  (16 * K + 2) * (TILE_X / 4 + 2) <= (TY + 2) * (TILE_X + 2),
+                  "narrow tiles fit the LDS arrays of the 64-wide tile");
     __shared__ C sphi[(TY + 2) * (TILE_X + 2)];
     // previous step's per-node terms with a two-node halo: (A, B, ux, uy) and (phi_w, H)
     __shared__ float4 sq[NR];
@@ -995,13 +1008,19 @@ __global__ __launch_bounds__(BLOCK) void k_step(
     const auto run = [&](int t) {
         const TileDesc T = tiles[t];
         const InstDev& I = insts[T.inst];
-        const bool interior = PULL && T.x0 >= 2 && T.x0 + TILE_X + 2 <= I.nx && T.y0 >= 2 &&
-                              T.y0 + TY + 2 <= I.ny;
+        const bool interior = PULL && T.pad == 0 && T.x0 >= 2 && T.x0 + TILE_X + 2 <= I.nx &&
+                              T.y0 >= 2 && T.y0 + TY + 2 <= I.ny;
         if (interior)
-            step_tile<S, K, PULL, MODE, RING_FROM_PLANE, true, QF>(
+            step_tile<S, K, PULL, MODE, RING_FROM_PLANE, true, QF, TILE_X>(
+                I, T, fsrc, gsrc, fdst, gdst, q, phiplane, msrc, mdst, mom_out, sphi, sq, sw);
+        else if (T.pad == 0)
+            step_tile<S, K, PULL, MODE, RING_FROM_PLANE, false, QF, TILE_X>(
+                I, T, fsrc, gsrc, fdst, gdst, q, phiplane, msrc, mdst, mom_out, sphi, sq, sw);
+        else if (T.pad == 1)
+            step_tile<S, K, PULL, MODE, RING_FROM_PLANE, false, QF, TILE_X / 2>(
                 I, T, fsrc, gsrc, fdst, gdst, q, phiplane, msrc, mdst, mom_out, sphi, sq, sw);
         else
-            step_tile<S, K, PULL, MODE, RING_FROM_PLANE, false, QF>(
+            step_tile<S, K, PULL, MODE, RING_FROM_PLANE, false, QF, TILE_X / 4>(
                 I, T, fsrc, gsrc, fdst, gdst, q, phiplane, msrc, mdst, mom_out, sphi, sq, sw);
     };
     const int b = blockIdx.x;
@@ -1036,17 +1055,19 @@ __global__ __launch_bounds__(BLOCK) void k_phi_plane(
     if (t >= ntiles) return;
     const TileDesc T = tiles[t];
     const InstDev& I = insts[T.inst];
-    const int w = min(TILE_X, I.nx - T.x0);
-    const int h = min(4 * K, I.ny - T.y0);
-    const int lx = threadIdx.x & (TILE_X - 1);
-    const int ly = threadIdx.x >> 6;
+    // tile width 64 >> T.pad, with 256 / width rows of threads (see k_step)
+    const int txw = TILE_X >> T.pad, rpg = BLOCK / txw;
+    const int w = min(txw, I.nx - T.x0);
+    const int h = min(rpg * K, I.ny - T.y0);
+    const int lx = threadIdx.x & (txw - 1);
+    const int ly = threadIdx.x >> (6 - T.pad);
     const S* fb = fsrc + I.off_dist;
     // phi_w, the first component of each node's (phi_w, p_w, ux_w, uy_w)
     const float4* rb = REF ? (const float4*)(msrc + I.off_mp) : nullptr;
     const C isf = C(I.inv_scale_f);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const int yl = ly + 4 * k;
+        const int yl = ly + rpg * k;
         if (lx < w && yl < h) {
             const int x = T.x0 + lx, y = T.y0 + yl;
             int o[9], src[9];

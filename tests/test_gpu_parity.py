@@ -241,6 +241,64 @@ def test_ragged_shapes_f64(nx, ny, bc):
     _check("random %dx%d %s" % (nx, ny, bc), c, 50, "f64")
 
 
+# widths whose last columns take 16-wide (r <= 16), 32-wide (r <= 32), 32 + 16-wide
+# (r <= 48) or 64-wide narrow-tile columns, heights not multiples of any tile height
+_RAGGED = [(3, 5), (17, 9), (40, 23), (70, 45), (100, 37), (113, 6), (127, 19), (130, 33),
+           (64, 11), (49, 70)]
+
+
+def _ragged_batch(seed=0):
+    batch = []
+    for j, (nx, ny) in enumerate(_RAGGED):
+        c = cases.random_state_case(nx, ny, seed=seed + j)
+        bc = ("periodic", "wall", "open")[j % 3]
+        if bc == "wall":
+            c["bc_ylo"] = c["bc_yhi"] = cases.WALL
+        elif bc == "open":
+            c["bc_ylo"], c["bc_yhi"] = cases.WALL, cases.OPEN
+        batch.append(c)
+    return batch
+
+
+@pytest.mark.parametrize("nx,ny", _RAGGED)
+def test_narrow_tiles_f64_bitwise_equal_to_oracle(nx, ny):
+    """Narrow tiles on the last columns of a ragged grid (every boundary type over the
+    widths), FP64 against the oracle bit for bit after 50 steps, at 4 and 8 rows."""
+    c = _ragged_batch()[_RAGGED.index((nx, ny))]
+    ref = run_oracle(c, 50)
+    for rows in (4, 8):
+        got = run_hip(c, 50, "f64", kernel="fused", tile_rows=rows, narrow="on")
+        for k in ref:
+            assert np.array_equal(got[k], ref[k]), (nx, ny, rows, k)
+
+
+@pytest.mark.parametrize("storage,qf", [("f64", 9), ("f32", 9), ("f16", 9), ("f32", 5)])
+def test_narrow_tiles_bitwise_identical(storage, qf):
+    """A batch of ragged grids (every boundary type) with narrow tiles on and off, at every
+    tile height, fused and split kernels, graph replay: the same bits."""
+    batch = _ragged_batch(seed=7)
+    if qf == 5:
+        for c in batch:
+            c["f_lattice"] = cases.D2Q5
+    ref = None
+    rows_set = (4, 8) if storage == "f64" else (4, 8, 16)
+    for rows in rows_set:
+        for kernel in ("fused", "split"):
+            for narrow in ("off", "on"):
+                with lbm.Simulation(batch, storage=storage, kernel=kernel, tile_rows=rows,
+                                    stores="cached", strip="rows", narrow=narrow) as sim:
+                    assert sim.info()["narrow"] == narrow
+                    sim.step(29)
+                    out = [sim.moments(k) for k in range(len(batch))]
+                if ref is None:
+                    ref = out
+                    continue
+                for k in range(len(batch)):
+                    for key in ref[k]:
+                        assert np.array_equal(out[k][key], ref[k][key]), (rows, kernel, narrow,
+                                                                          k, key)
+
+
 @pytest.mark.parametrize("law", [cases.NU_LINEAR, cases.NU_INVERSE, cases.MU_STEP])
 def test_viscosity_laws_f64(law):
     c = cases.random_state_case(40, 24, seed=5, visc_law=law)
