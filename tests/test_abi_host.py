@@ -107,8 +107,9 @@ def test_instance_beyond_4gib_rejected_before_device(storage, n):
 def test_null_context_calls():
     L = lbm.load()
     assert L.lbm_step(None, 1) == lbm.LBM_ERR_PARAM
-    assert L.lbm_info(None, None, None, None, None, None, None) == lbm.LBM_ERR_PARAM
+    assert L.lbm_info(None, None, None, None, None, None, None, None) == lbm.LBM_ERR_PARAM
     assert L.lbm_reduce(None, 0, None, None) == lbm.LBM_ERR_PARAM
+    assert L.lbm_reduce_noalloc(None, 0, None, None) == lbm.LBM_ERR_PARAM
     L.lbm_destroy(None)
     assert lbm.lbm_last_error()
 
