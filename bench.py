@@ -322,10 +322,10 @@ def batch_cpu_baseline(cs, steps, every=16):
 def batch_accuracy(cs, storage, steps, refs, r, masks):
     """Per-instance max-norm errors (phi, u, p) of the batched GPU run after `steps` steps
     against the oracle run of each sampled instance alone, in the launch configuration `r`
-    of the timed run (no autotuning).  phi and p are also given outside the nodes near each
-    drop's centre (masks, tests/parity.drop_centre_mask: a disc fixed from the case alone,
-    where the oracle itself cannot be followed to the FP32 tolerance); the tolerance is
-    judged there, and on u everywhere."""
+    of the timed run (no autotuning).  phi and p are also given outside each drop's interior
+    plateau (masks, tests/parity.drop_interior_mask: a disc fixed from the case alone, where
+    the oracle itself cannot be followed to the FP32 tolerance); the tolerance is judged
+    there, and on u everywhere."""
     from paper_1710_09541_amd import lbm
     from tests.parity import errors, errors_outside
     strip = "rows" if r["tile_order"] == "rows" else int(r["tile_order"].split()[2])
@@ -345,8 +345,8 @@ def batch_accuracy(cs, storage, steps, refs, r, masks):
     tol = TOL[storage]
     ok = judged["u"] <= tol and (storage == "f16" or judged["phi"] <= tol)
     return {"steps": steps, "instances": sorted(refs), "max_err": worst,
-            "max_err_outside_drop_centres": judged,
-            "nodes_near_drop_centres": int(sum(int(m.sum()) for m in masks.values()
+            "max_err_outside_drop_interiors": judged,
+            "nodes_in_drop_interiors": int(sum(int(m.sum()) for m in masks.values()
                                                if m is not None)),
             "tol": tol, "within_tol": bool(ok)}
 
@@ -458,8 +458,8 @@ def main():
             log("%s: accuracy %s" % (st, json.dumps(r["accuracy_vs_oracle"])))
         if batch_refs is not None:
             if batch_masks is None:
-                from tests.parity import drop_centre_mask
-                batch_masks = {k: drop_centre_mask(cs[k], cpu_steps + 1) for k in batch_refs}
+                from tests.parity import drop_interior_mask
+                batch_masks = {k: drop_interior_mask(cs[k], cpu_steps + 1) for k in batch_refs}
             r["accuracy_vs_oracle"] = batch_accuracy(cs, st, cpu_steps + 1, batch_refs, r,
                                                      batch_masks)
             log("%s: per-instance accuracy %s" % (st, json.dumps(r["accuracy_vs_oracle"])))
