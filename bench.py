@@ -16,8 +16,9 @@ reported next to it.  Each format states its error against the FP64 CPU oracle:
 The roofline fraction counts the algorithmic bytes of the method: every population read
 and written once, phi written and read once and phi u of the previous step read and
 written once (168 B per lattice update in FP32, 336 in FP64, 96 with 16-bit
-populations).  The kernel's own design moves a 16-byte per-node state each way instead of
-the phi plane and phi u (176 / 320 / 104 B); that figure is reported beside it.
+populations).  The kernel's own design moves a per-node state each way instead of the phi
+plane and phi u: 12 bytes in FP32 (phi_w, u_w), 16 in FP64 (phi u) and with 16-bit
+populations (phi_w, p_w, u_w), so 168 / 320 / 104 B; that figure is reported beside it.
 
 Also timed (unless --no-extra):
 * the spinodal decomposition 1024 x 1024 (the earlier headline; phi0 = 0.5 + U[-0.01, 0.01],
@@ -52,10 +53,11 @@ ESIZE = {"f64": 8, "f32": 4, "f16": 2}
 def alg_bytes(storage, qf=9):
     """Bytes per lattice update that the fused step kernel moves by design, with a
     phase-field lattice of qf velocities: qf f and 9 g populations read and written once,
-    plus the per-node state beside them read and written once (32 bytes: FP64 phi u of the
-    previous step, 2 doubles; the reduced formats' FP32 planes phi_w, p_w, ux_w, uy_w).
-    D2Q9: FP64 320, FP32 176, FP16 104."""
-    return 2 * (qf + 9) * ESIZE[storage] + 32
+    plus the per-node state beside them read and written once (FP64: phi u of the previous
+    step, 2 doubles; FP32: phi_w, ux_w, uy_w, 3 floats; 16-bit: phi_w, p_w, ux_w, uy_w,
+    4 floats).  D2Q9: FP64 320, FP32 168, FP16 104."""
+    state = {"f64": 16, "f32": 12, "f16": 16}[storage]
+    return 2 * (qf + 9) * ESIZE[storage] + 2 * state
 
 
 def method_bytes(storage, qf=9):

@@ -30,7 +30,7 @@ namespace {
 thread_local std::string g_thread_err;
 
 constexpr uint64_t STATE_MAGIC = 0x4c424d5046534154ull;  // "LBMPFSAT"
-constexpr int STATE_VERSION = 5;
+constexpr int STATE_VERSION = 6;
 // steps per captured graph, shortest first: each graph launch costs a few microseconds
 // between the last kernel of one graph and the first of the next, which long graphs spread
 // over more steps (measured: 64 steps per graph 0.6 % faster than 16 at 1024^2 FP32 and 4 %
@@ -94,8 +94,9 @@ struct lbm_ctx {
     int64_t dist_elems = 0;    // elements of one distribution set (all instances, 9 planes)
     int64_t q_elems = 0;       // FP64 phi u: a double2 per node and instance
     int64_t phi_elems = 0;     // split-kernel phi: 1 plane per instance
-    int64_t mp_elems = 0;      // per-node state, in floats: reduced formats, a float4 per node
-                               // and instance; FP64, two rows of doubles per instance
+    int64_t mp_elems = 0;      // per-node state, in floats: 16-bit format, a float4 per node;
+                               // FP32, a float3 per node and two rows of floats per instance;
+                               // FP64, two rows of doubles per instance
     void* f[2] = {nullptr, nullptr};
     void* g[2] = {nullptr, nullptr};
     void* q = nullptr;
@@ -844,12 +845,15 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
         I.d.off_mp = off_mp;
         off_dist += round_up(9 * I.d.plane, 64);
         // phi u of the previous step: two double planes (FP64 format) or, in the reduced
-        // formats, the per-node FP32 (phi_w, p_w, ux_w, uy_w) that also carries it.  The FP64
-        // format keeps the pressure of its first and last rows for open sides in that place:
-        // two rows of pitch doubles, double-buffered like the reduced formats' planes.
+        // formats, the per-node FP32 state that also carries it: (phi_w, p_w, ux_w, uy_w) in
+        // the 16-bit format, (phi_w, ux_w, uy_w) and the pressure of the first and the last
+        // row (open sides) in the FP32 format.  The FP64 format keeps the pressure of those
+        // rows in that place: two rows of pitch doubles.  All double-buffered.
         if (c->storage == STORE_F64) {
             off_q += round_up(2 * I.d.plane, 64);
             off_mp += round_up(2 * 2 * (int64_t)I.d.pitch, 64);
+        } else if (c->storage == STORE_F32) {
+            off_mp += round_up(3 * I.d.plane + 2 * (int64_t)I.d.pitch, 64);
         } else {
             off_mp += round_up(4 * I.d.plane, 64);
         }

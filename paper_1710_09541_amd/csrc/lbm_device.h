@@ -23,9 +23,11 @@ struct InstDev {
     int64_t off_dist;   // offset of this instance's plane 0 in the f and g arrays
     int64_t off_q;      // FP64 format: offset of its two (phi u) planes in the q array
     int64_t off_phi;    // offset of its phi plane (split kernel)
-    int64_t off_mp;     // offset (in floats) of its per-node state: reduced formats, the
-                        // planes phi_w, p_w, ux_w, uy_w; FP64, two rows of doubles holding
-                        // the pressure of the first and the last row (open sides)
+    int64_t off_mp;     // offset (in floats) of its per-node state: 16-bit format, a float4
+                        // (phi_w, p_w, ux_w, uy_w) per node; FP32, a float3 (phi_w, ux_w,
+                        // uy_w) per node, then two rows of floats holding the pressure of the
+                        // first and the last row (open sides); FP64, only those two rows, of
+                        // doubles
     int64_t plane;      // ny * pitch
     double rho_l, rho_g, drho;      // drho = rho_l - rho_g
     double nu_l, nu_g, inv_nu_l, inv_nu_g, mu_l, mu_g;

@@ -12,10 +12,11 @@
 // in place instead of pulling.
 //
 // Storage.  FP64: the populations themselves, and phi u of the previous step.  FP32 /
-// FP16 ("equilibrium deviation"): every node also writes, as one float4, its phi_w, p_w
-// and u_w (phi, p, u rounded to FP32).  An f slot holds (f_i - w_i phi_w) 2^exp_f and a g
-// slot (g_i - g^eq_i(rho(phi_w), p_w, u_w)) 2^exp_g, both taken at the node that wrote the
-// slot.  A reader decodes a pulled population with the (phi_w, p_w, u_w) of its source node,
+// FP16 ("equilibrium deviation"): every node also writes its phi_w and u_w (phi and u
+// rounded to FP32) and, in the 16-bit format, p_w, as one float3 or float4.  An f slot
+// holds (f_i - w_i phi_w) 2^exp_f and a g slot (g_i - g^eq_i(rho(phi_w), p_w, u_w)) 2^exp_g
+// (p_w = 0 in the FP32 format), both taken at the node that wrote the slot.  A reader
+// decodes a pulled population with the (phi_w, p_w, u_w) of its source node,
 // staged with a two-node halo in LDS; the g equilibrium is evaluated by one function,
 // identically on both sides.  The moments, and the momentum the g relaxation must keep,
 // are formed in FP64.  The stored numbers are thus the small
@@ -174,6 +175,21 @@ struct Buf<_Float16> {
 template <typename S>
 constexpr bool rest_deviation() {
     return sizeof(S) < sizeof(double);
+}
+
+// Per-node state of the reduced formats.  The 16-bit format keeps (phi_w, p_w, ux_w, uy_w),
+// one float4 per node, and its g reference equilibrium holds p_w: a g slot rounded to 11
+// bits relative must not carry the full pressure part 3 w_i p.  The FP32 format keeps
+// (phi_w, ux_w, uy_w), one float3 per node, and references g to the equilibrium at p = 0:
+// 24 bits hold that part with room to spare.  Its open sides need the pressure of the edge
+// rows of the previous step, two rows of floats after the nodes' state.
+template <typename S>
+constexpr bool ref_has_p() {
+    return sizeof(S) < sizeof(float);
+}
+template <typename S>
+constexpr int state_floats() {
+    return ref_has_p<S>() ? 4 : 3;
 }
 
 // ------------------------------------------------------------------ streaming offsets
@@ -497,8 +513,9 @@ __device__ __forceinline__ float geq_ref(int i, float A, float B, float ux, floa
 // populations sum to phi + res); qx, qy: phi_w u_w of this node at the previous step.
 // Writes the collided e_i into fo, the g deviations g*_i - g^eq_i(published moments) into
 // go and the published p_w, u_w into pw, or the moments into mom.  FIRST: the state is the
-// initial one, f = f^eq(phi0, u0) and g = g^eq(p = 0, u0) at every node.
-template <int MODE, bool FIRST, int QF>
+// initial one, f = f^eq(phi0, u0) and g = g^eq(p = 0, u0) at every node.  REFP: the g
+// reference holds the published p_w (16-bit format); otherwise p = 0 (FP32 format).
+template <int MODE, bool FIRST, int QF, bool REFP>
 __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&f)[9],
                                                 const float (&eg)[9], const float (&gs)[9],
                                                 float phi, float pE, float pN, float pW,
@@ -634,12 +651,14 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
     fo[0] = res - t;
 
     // g collision (Eqs. 15-17, 20) on deviations from the published equilibrium gw:
-    // g*_i - gw_i = (1 - 1/tau_g)(g_i - gw_i) + G_i + (1/tau_g)(g^eq_i - gw_i).  Of the last
-    // term, which only reflects the FP32 rounding of the published moments, the part that
-    // carries momentum is kept exactly (a 3 w_i c_i.dj correction with dj = rho u -
-    // sum_i c_i gw_i formed in FP64), so the collision conserves momentum to FP32 rounding of
-    // small deviations and a weak body force is not lost to rounding.
-    const RefTerms R = ref_terms(I, phi, cp, cux, cuy);
+    // g*_i - gw_i = (1 - 1/tau_g)(g_i - gw_i) + G_i + (1/tau_g)(g^eq_i - gw_i).  The last
+    // term holds the FP32 rounding of the published moments and, where the reference is
+    // taken at p = 0 (REFP false), the pressure part of the equilibrium, 3 p (w_i - [i = 0])
+    // (Eq. 16), which is added as such.  Of the rounding, the part that carries momentum is
+    // kept exactly (a 3 w_i c_i.dj correction with dj = rho u - sum_i c_i gw_i formed in
+    // FP64), so the collision conserves momentum to FP32 rounding of small deviations and a
+    // weak body force is not lost to rounding.
+    const RefTerms R = ref_terms(I, phi, REFP ? cp : 0.0f, cux, cuy);
     float gw[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) gw[i] = geq_ref(i, R.A, R.B, cux, cuy, R.H);
@@ -659,6 +678,7 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
     const C cg = C(1) - C(0.5) * inv_tau_g;
     const C keep = C(1) - inv_tau_g;
     const C drho3 = C(3) * C(I.drho);
+    const C pt = REFP ? C(0) : inv_tau_g * (C(3) * cp);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const C w = wgt<C>(i);
@@ -667,6 +687,7 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
                        drho3 * dotc<C>(i, cux, cuy) * dotc<C>(i, dpx, dpy));
         const C d = eg[i] + (gs[i] - gw[i]);
         go[i] = keep * d + frc + w * dotc<C>(i, cjx, cjy);
+        if (!REFP) go[i] += (i == 0 ? w - C(1) : w) * pt;
     }
 }
 
@@ -675,8 +696,8 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
 // f and g of its K nodes and puts their phi into an LDS tile; the block recomputes phi on
 // the one-node halo ring from pulled f (neighbouring tiles' data, mostly L2 hits), and
 // after a barrier every node has its 3 x 3 phi neighbourhood in LDS.  In the reduced
-// formats the block first stages the previous step's four planes (phi_w, p_w, u_w) over
-// the tile plus two nodes into LDS, to decode the pulled populations.
+// formats the block first stages the previous step's per-node state (phi_w, u_w and, 16-bit
+// format, p_w) over the tile plus two nodes into LDS, to decode the pulled populations.
 //
 // Block b runs tile (b % 8) * per_xcd + b / 8: the hardware deals blocks round-robin to
 // the 8 XCDs, so each XCD walks one contiguous run of tiles and finds the halo rows of
@@ -688,9 +709,11 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
 // k_phi_plane instead of being recomputed.
 //
 // q: FP64 format, phi u of the previous step (one double2 per node, updated in place).
-// msrc / mdst: reduced formats, every node's (phi_w, p_w, ux_w, uy_w) as one float4, of the
-// previous step (read) and of this step (written); FP64 format, the pressure of the first
-// and the last row (two rows of doubles), which an open side needs.
+// msrc / mdst: the per-node state of the previous step (read) and of this step (written):
+// 16-bit format, (phi_w, p_w, ux_w, uy_w) as one float4 per node; FP32 format,
+// (phi_w, ux_w, uy_w) as one float3 per node, then the pressure of the first and the last
+// row (two rows of floats); FP64 format, only those two rows, of doubles.  An open side
+// needs the edge rows' pressure.
 template <typename S, int K, bool PULL, int MODE, bool RING_FROM_PLANE, bool INTERIOR, int QF,
           int TXW>
 __device__ __forceinline__ void step_tile(
@@ -701,6 +724,7 @@ __device__ __forceinline__ void step_tile(
     typename Store<S>::C* sphi, float4* sq, float2* sw) {
     using C = typename Store<S>::C;
     constexpr bool REF = rest_deviation<S>();
+    constexpr bool REFP = ref_has_p<S>();
     constexpr bool SCALED = sizeof(S) < sizeof(float);   // only the 16-bit format is scaled
     // a stored 16-bit value times 2^-exp as one fused multiply-add that reads it directly
     // (the product is exact; with no scale the value is used as it is)
@@ -756,9 +780,21 @@ __device__ __forceinline__ void step_tile(
                 gy %= ny;
                 gy = gy < 0 ? gy + ny : gy;
             }
-            const float4 m4 = ld((const float4*)mb, gy * pitch + gx);
-            const float ph = m4.x;
-            const RefTerms R = ref_terms(I, ph, m4.y, m4.z, m4.w);
+            float ph, pp, ux, uy;
+            if constexpr (REFP) {
+                const float4 m4 = ld((const float4*)mb, gy * pitch + gx);
+                ph = m4.x;
+                pp = m4.y;
+                ux = m4.z;
+                uy = m4.w;
+            } else {
+                const float3 m3 = ld((const float3*)mb, gy * pitch + gx);
+                ph = m3.x;
+                pp = 0.0f;
+                ux = m3.y;
+                uy = m3.z;
+            }
+            const RefTerms R = ref_terms(I, ph, pp, ux, uy);
             sq[idx] = make_float4(R.A, R.B, R.ux, R.uy);
             sw[idx] = make_float2(ph, R.H);
         }
@@ -914,20 +950,42 @@ __device__ __forceinline__ void step_tile(
                 if (i < QF) fd[i] = __builtin_fmaf(wf<float, QF>(i), q2.x - phi, unscale(f[k][i], isf));
                 eg[i] = unscale(g[k][i], isg);
                 // decoded against the source node's equilibrium, at the ambient pressure 0 for
-                // a population entering through an open side: g*_i(s) + (0 - p_w(s)) w_i / c_s^2
+                // a population entering through an open side: g*_i(s) + (0 - p(s)) w_i / c_s^2.
+                // The 16-bit format's reference holds p_w(s); the FP32 format's holds 0 and
+                // takes p(s) from the edge-pressure row.
                 const bool amb = (open_lo && CY[i] > 0) || (open_hi && CY[i] < 0);
-                gs[i] = geq_ref(dir[i], q4.x, amb ? 0.0f : q4.y, q4.z, q4.w, q2.y);
+                float B = q4.y;
+                if (amb) {
+                    if constexpr (REFP) {
+                        B = 0.0f;
+                    } else {
+                        const float* pe = msrc + I.off_mp + 3 * (int64_t)plane + (open_hi ? pitch : 0);
+                        int xs = x - CX[i];
+                        xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+                        B = -3.0f * pe[xs];
+                    }
+                }
+                gs[i] = geq_ref(dir[i], q4.x, B, q4.z, q4.w, q2.y);
             }
             const int me = (yl + 2) * RW + lx + 2;
             const float qx = sw[me].x * sq[me].z, qy = sw[me].x * sq[me].w;
-            node_update_ref<MODE, !PULL, QF>(I, fd, eg, gs, phi, r1[2], r2[1], r1[0], r0[1], r2[2], r2[0],
+            node_update_ref<MODE, !PULL, QF, REFP>(I, fd, eg, gs, phi, r1[2], r2[1], r1[0], r0[1], r2[2], r2[0],
                                   r0[0], r0[2], res[k], qx, qy, fo, go, pw, mom);
             if (MODE != MODE_MOMENTS) {
 #pragma unroll
                 for (int i = 0; i < QF; ++i) put_pop<MODE>(rfo, fo_b, i * plane, self, fo[i] * sf);
 #pragma unroll
                 for (int i = 0; i < 9; ++i) put_pop<MODE>(rgo, go_b, i * plane, self, go[i] * sgs);
-                st((float4*)(mdst + I.off_mp), self, make_float4(phi, pw[0], pw[1], pw[2]));
+                if constexpr (REFP) {
+                    st((float4*)(mdst + I.off_mp), self, make_float4(phi, pw[0], pw[1], pw[2]));
+                } else {
+                    st((float3*)(mdst + I.off_mp), self, make_float3(phi, pw[1], pw[2]));
+                    // the pressure of an edge row on an open side, for the populations that
+                    // enter through it at the next step
+                    if (!INTERIOR && ((y == 0 && I.bc_lo == BC_OPEN) ||
+                                      (y == ny - 1 && I.bc_hi == BC_OPEN)))
+                        st(mdst + I.off_mp + 3 * (int64_t)plane, (y == 0 ? 0 : pitch) + x, pw[0]);
+                }
             }
         } else {
             // phi u of the previous step, one double2 per node
@@ -1062,8 +1120,9 @@ __global__ __launch_bounds__(BLOCK) void k_phi_plane(
     const int lx = threadIdx.x & (txw - 1);
     const int ly = threadIdx.x >> (6 - T.pad);
     const S* fb = fsrc + I.off_dist;
-    // phi_w, the first component of each node's (phi_w, p_w, ux_w, uy_w)
-    const float4* rb = REF ? (const float4*)(msrc + I.off_mp) : nullptr;
+    // phi_w, the first component of each node's state (3 or 4 floats)
+    constexpr int NSF = state_floats<S>();
+    const float* rb = REF ? msrc + I.off_mp : nullptr;
     const C isf = C(I.inv_scale_f);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -1077,8 +1136,8 @@ __global__ __launch_bounds__(BLOCK) void k_phi_plane(
             for (int i = 0; i < QF; ++i) v[i] = Store<S>::get(fb, o[i]);
             if (REF) {
 #pragma unroll
-                for (int i = 0; i < QF; ++i) ref[i] = rb[src[i]].x;
-                base = rb[y * I.pitch + x].x;
+                for (int i = 0; i < QF; ++i) ref[i] = rb[(int64_t)src[i] * NSF];
+                base = rb[(int64_t)(y * I.pitch + x) * NSF];
             }
             phiplane[I.off_phi + y * I.pitch + x] =
                 phi_of<C, REF, QF, (sizeof(S) < sizeof(float))>(v, ref, base, isf);
@@ -1098,7 +1157,7 @@ __device__ __forceinline__ double init_rho(double ph, double drho, double rho_g)
 
 // f = f^eq(phi0, u0) (Eq. 9), g = g^eq(p = 0, u0) with rho(phi0) (Eq. 16), phi u = phi0 u0,
 // in the storage format, already in streamed form (FP64: q planes; reduced formats: the
-// planes phi_w, p_w = 0, u_w and deviations from them).
+// per-node phi_w, u_w (and p_w = 0 in the 16-bit format) and deviations from them).
 template <typename S, int QF>
 __global__ __launch_bounds__(BLOCK) void k_init(const InstDev* __restrict__ insts, int inst,
                                                 const double* __restrict__ phi0,
@@ -1143,8 +1202,11 @@ __global__ __launch_bounds__(BLOCK) void k_init(const InstDev* __restrict__ inst
             Store<S>::put(gb, i * plane + self, (C)ge);
         }
     }
-    if (REF) {
+    if constexpr (ref_has_p<S>()) {
         ((float4*)(mp + I.off_mp))[self] = make_float4(phw, 0.0f, uxw, uyw);
+    } else if constexpr (REF) {
+        // the edge-pressure rows after the nodes' state start at p = 0 (cleared at set-up)
+        ((float3*)(mp + I.off_mp))[self] = make_float3(phw, uxw, uyw);
     } else {
         ((double2*)(q + I.off_q))[self] = make_double2(ph * ux, ph * uy);
     }

@@ -18,12 +18,13 @@ def test_more_than_one_gpu_refused_with_a_message():
 
 def test_algorithmic_bytes_per_lattice_update():
     # 18 population values read and 18 written, plus the per-node state (FP64: phi u read and
-    # written, 2 x 2 x 8 B; reduced formats: one float4 read and one written, 2 x 16 B)
+    # written, 2 x 2 x 8 B; FP32: one float3 read and one written, 2 x 12 B; 16-bit: one
+    # float4 read and one written, 2 x 16 B)
     assert bench.alg_bytes("f64", 9) == 36 * 8 + 32
-    assert bench.alg_bytes("f32", 9) == 36 * 4 + 32
+    assert bench.alg_bytes("f32", 9) == 36 * 4 + 24
     assert bench.alg_bytes("f16", 9) == 36 * 2 + 32
     # D2Q5 phase field: 14 populations per node instead of 18
-    assert bench.alg_bytes("f32", 5) == 28 * 4 + 32
+    assert bench.alg_bytes("f32", 5) == 28 * 4 + 24
 
 
 def test_code_hash_ignores_comments_and_blank_space():
