@@ -256,6 +256,26 @@ void fill_inst(Instance& I, int storage, const double* phi0, const double* ux0, 
     I.p.exp_f = ef;
     I.p.exp_g = eg;
     I.n_nodes = n;
+    // FP32 copies of the constants (lbm_device.h): the same roundings the kernels would make
+    d.f_beta4 = (float)(4.0 * d.beta);
+    d.f_kappa = (float)d.kappa;
+    d.f_inv_w = (float)d.inv_w;
+    d.f_dnu = (float)(d.nu_l - d.nu_g);
+    d.f_nu_g = (float)d.nu_g;
+    d.f_dinv_nu = (float)(d.inv_nu_l - d.inv_nu_g);
+    d.f_inv_nu_g = (float)d.inv_nu_g;
+    d.f_mu_l = (float)d.mu_l;
+    d.f_mu_g = (float)d.mu_g;
+    d.f_Gx = (float)d.Gx;
+    d.f_Gy = (float)d.Gy;
+    d.f_inv_tau_f = (float)d.inv_tau_f;
+    d.f_cf = (float)d.cf;
+    d.f_drho = (float)d.drho;
+    d.f_rho_g = (float)d.rho_g;
+    d.f_scale_f = (float)d.scale_f;
+    d.f_inv_scale_f = (float)d.inv_scale_f;
+    d.f_scale_g = (float)d.scale_g;
+    d.f_inv_scale_g = (float)d.inv_scale_g;
 }
 
 // Narrow tiles for the last r = nx mod 64 columns of an instance (narrow = true): 16 wide

@@ -35,6 +35,13 @@ struct InstDev {
     double tau_f, inv_tau_f, cf;    // tau_phi, 1 / tau_phi and 1 - 1 / (2 tau_phi)
     double Gx, Gy;
     double scale_f, inv_scale_f, scale_g, inv_scale_g;  // storage scales 2^exp
+    // FP32 copies for the reduced formats' arithmetic, each rounded on the host from the FP64
+    // expression the kernels would otherwise round in every lane (the same bits): 4 beta,
+    // kappa, 1 / W, nu_l - nu_g, nu_g, 1/nu_l - 1/nu_g, 1/nu_g, mu_l, mu_g, Gx, Gy, 1/tau_phi,
+    // 1 - 1/(2 tau_phi), rho_l - rho_g, rho_g and the four storage scales
+    float f_beta4, f_kappa, f_inv_w, f_dnu, f_nu_g, f_dinv_nu, f_inv_nu_g, f_mu_l, f_mu_g;
+    float f_Gx, f_Gy, f_inv_tau_f, f_cf, f_drho, f_rho_g;
+    float f_scale_f, f_inv_scale_f, f_scale_g, f_inv_scale_g;
 };
 
 // One tile of one instance: origin (x0, y0) and width class pad: 0 for TILE_X nodes wide

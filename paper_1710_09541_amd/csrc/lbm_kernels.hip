@@ -491,7 +491,7 @@ __device__ __forceinline__ RefTerms ref_terms(const InstDev& I, float phi, float
                                               float uy) {
 #pragma clang fp contract(off)
     RefTerms r;
-    r.A = __builtin_fmaf(phi, (float)I.drho, (float)I.rho_g);
+    r.A = __builtin_fmaf(phi, I.f_drho, I.f_rho_g);
     r.B = p * 3.0f;
     r.ux = ux;
     r.uy = uy;
@@ -514,8 +514,9 @@ __device__ __forceinline__ float geq_ref(int i, float A, float B, float ux, floa
 // Writes the collided e_i into fo, the g deviations g*_i - g^eq_i(published moments) into
 // go and the published p_w, u_w into pw, or the moments into mom.  FIRST: the state is the
 // initial one, f = f^eq(phi0, u0) and g = g^eq(p = 0, u0) at every node.  REFP: the g
-// reference holds the published p_w (16-bit format); otherwise p = 0 (FP32 format).
-template <int MODE, bool FIRST, int QF, bool REFP>
+// reference holds the published p_w (16-bit format); otherwise p = 0 (FP32 format).  M32:
+// the moments in FP32 (16-bit format), otherwise in FP64.
+template <int MODE, bool FIRST, int QF, bool REFP, bool M32>
 __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&f)[9],
                                                 const float (&eg)[9], const float (&gs)[9],
                                                 float phi, float pE, float pN, float pW,
@@ -530,10 +531,17 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
     const C lap = C(6) * (C(1.0 / 9.0) * ((pE + pW) + (pN + pS) - C(4) * phi) +
                           C(1.0 / 36.0) * ((pNE + pSW) + (pNW + pSE) - C(4) * phi));
 
-    // closure (S3): rho (Eq. 13) in FP64, mu_phi (Eqs. 6-7), lambda (Eq. 3), n (Eq. 2)
-    const double rho = (double)phi * I.drho + I.rho_g;
-    const C mu_phi = C(4.0 * I.beta) * phi * (phi - C(1)) * (phi - C(0.5)) - C(I.kappa) * lap;
-    const C lam = C(4) * phi * (C(1) - phi) * C(I.inv_w);
+    // closure (S3): rho (Eq. 13), mu_phi (Eqs. 6-7), lambda (Eq. 3), n (Eq. 2)
+    double rho64 = 0.0;
+    C rho;
+    if constexpr (M32) {
+        rho = __builtin_fmaf(phi, I.f_drho, I.f_rho_g);
+    } else {
+        rho64 = (double)phi * I.drho + I.rho_g;
+        rho = C(rho64);
+    }
+    const C mu_phi = I.f_beta4 * phi * (phi - C(1)) * (phi - C(0.5)) - I.f_kappa * lap;
+    const C lam = C(4) * phi * (C(1) - phi) * I.f_inv_w;
     const C mag2 = dpx * dpx + dpy * dpy;
     C nx_ = C(0), ny_ = C(0);
     if (mag2 > C(1e-24)) {   // |grad phi| > 1e-12
@@ -543,54 +551,103 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
     }
     C nu;
     if (I.visc_law == VISC_LINEAR) {
-        nu = phi * C(I.nu_l - I.nu_g) + C(I.nu_g);
+        nu = phi * I.f_dnu + I.f_nu_g;
     } else if (I.visc_law == VISC_INVERSE) {
-        nu = rcp(phi * C(I.inv_nu_l - I.inv_nu_g) + C(I.inv_nu_g));
+        nu = rcp(phi * I.f_dinv_nu + I.f_inv_nu_g);
     } else {
-        nu = (phi >= C(0.5) ? C(I.mu_l) : C(I.mu_g)) * rcp(C(rho));
+        nu = (phi >= C(0.5) ? I.f_mu_l : I.f_mu_g) * rcp(rho);
     }
     const C inv_tau_g = rcp(C(3) * nu + C(0.5));       // Eq. 23
-    const C Fx = mu_phi * dpx + C(I.Gx);               // Eqs. 5, 19
-    const C Fy = mu_phi * dpy + C(I.Gy);
+    const C Fx = mu_phi * dpx + I.f_Gx;                // Eqs. 5, 19
+    const C Fy = mu_phi * dpy + I.f_Gy;
 
-    // moments in FP64 (Eq. 22): u first, then p
-    double G[9];
+    // moments (Eq. 22), u first, then p.
+    // M32 (16-bit format): in FP32.  Each population is its stored deviation plus the source's
+    // reference equilibrium, rounded relative to that reference, so u and p carry errors of
+    // the order of their own FP32 rounding, far below the format's own.  Momentum
+    // conservation does not rest on them: the collision's momentum correction below is
+    // formed from the same FP32 deviations it relaxes.
+    // Otherwise (FP32 format): in FP64 from the exact sums of the FP32 parts.
+    C cux, cuy, cp, irho;
+    double mx = 0.0, my = 0.0;
+    if constexpr (M32) {
+        C G[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) G[i] = (double)eg[i] + (double)gs[i];
-    double jx = G[1];
-    jx -= G[3];
-    jx += G[5];
-    jx -= G[6];
-    jx -= G[7];
-    jx += G[8];
-    double jy = G[2];
-    jy -= G[4];
-    jy += G[5];
-    jy += G[6];
-    jy -= G[7];
-    jy -= G[8];
-    const double mx = jx + 0.5 * (double)Fx, my = jy + 0.5 * (double)Fy;   // rho u
-    const double irho = 1.0 / rho;
-    const double ux = mx * irho;
-    const double uy = my * irho;
-    double sg = G[1];
+        for (int i = 0; i < 9; ++i) G[i] = eg[i] + gs[i];
+        C jx = G[1];
+        jx -= G[3];
+        jx += G[5];
+        jx -= G[6];
+        jx -= G[7];
+        jx += G[8];
+        C jy = G[2];
+        jy -= G[4];
+        jy += G[5];
+        jy += G[6];
+        jy -= G[7];
+        jy -= G[8];
+        irho = rcp(rho);
+        const C ux = (jx + C(0.5) * Fx) * irho;   // (rho u) / rho
+        const C uy = (jy + C(0.5) * Fy) * irho;
+        C sg = G[1];
 #pragma unroll
-    for (int i = 2; i < 9; ++i) sg += G[i];
-    const double uu = ux * ux + uy * uy;
-    const double pr = 0.6 * (sg + 0.5 * I.drho * (ux * (double)dpx + uy * (double)dpy) -
-                             (2.0 / 3.0) * rho * uu);
-
-    if (MODE == MODE_MOMENTS) {
-        mom[0] = (double)phi;
-        mom[1] = rho;
-        mom[2] = pr;
-        mom[3] = ux;
-        mom[4] = uy;
-        return;
+        for (int i = 2; i < 9; ++i) sg += G[i];
+        const C uu = ux * ux + uy * uy;
+        const C pr = C(0.6) * (sg + C(0.5) * I.f_drho * (ux * dpx + uy * dpy) -
+                               C(2.0 / 3.0) * rho * uu);
+        if (MODE == MODE_MOMENTS) {
+            mom[0] = (double)phi;
+            mom[1] = (double)rho;
+            mom[2] = (double)pr;
+            mom[3] = (double)ux;
+            mom[4] = (double)uy;
+            return;
+        }
+        cux = ux;
+        cuy = uy;
+        cp = pr;
+    } else {
+        double G[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) G[i] = (double)eg[i] + (double)gs[i];
+        double jx = G[1];
+        jx -= G[3];
+        jx += G[5];
+        jx -= G[6];
+        jx -= G[7];
+        jx += G[8];
+        double jy = G[2];
+        jy -= G[4];
+        jy += G[5];
+        jy += G[6];
+        jy -= G[7];
+        jy -= G[8];
+        mx = jx + 0.5 * (double)Fx;   // rho u
+        my = jy + 0.5 * (double)Fy;
+        const double irho64 = 1.0 / rho64;
+        const double ux = mx * irho64;
+        const double uy = my * irho64;
+        double sg = G[1];
+#pragma unroll
+        for (int i = 2; i < 9; ++i) sg += G[i];
+        const double uu = ux * ux + uy * uy;
+        const double pr = 0.6 * (sg + 0.5 * I.drho * (ux * (double)dpx + uy * (double)dpy) -
+                                 (2.0 / 3.0) * rho64 * uu);
+        if (MODE == MODE_MOMENTS) {
+            mom[0] = (double)phi;
+            mom[1] = rho64;
+            mom[2] = pr;
+            mom[3] = ux;
+            mom[4] = uy;
+            return;
+        }
+        cux = C(ux);
+        cuy = C(uy);
+        cp = C(pr);
+        irho = C(irho64);
     }
 
     // the FP32 moments this node publishes (and encodes its g against)
-    const C cux = C(ux), cuy = C(uy), cp = C(pr);
     pw[0] = cp;
     pw[1] = cux;
     pw[2] = cuy;
@@ -608,7 +665,7 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
         // moment, so the first step takes the closed form.
         C cx, cy;
         if (FIRST) {
-            const C k = C(-0.25) * phi * C(irho);
+            const C k = C(-0.25) * phi * irho;
             cx = k * Fx;
             cy = k * Fy;
         } else {
@@ -634,7 +691,7 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
     // before and after the collision (sum f^eq = phi, sum F_i = 0); the rest population is
     // taken from that invariant, so neither the rounding of phi nor the inexact FP32 weights
     // can bias the total phi.
-    const C itf = C(I.inv_tau_f), cf = C(I.cf);
+    const C itf = I.f_inv_tau_f, cf = I.f_cf;
     const C ax = C(3) * Dx + lam * nx_;
     const C ay = C(3) * Dy + lam * ny_;
     const C phi3 = C(3) * phi;
@@ -655,29 +712,54 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
     // term holds the FP32 rounding of the published moments and, where the reference is
     // taken at p = 0 (REFP false), the pressure part of the equilibrium, 3 p (w_i - [i = 0])
     // (Eq. 16), which is added as such.  Of the rounding, the part that carries momentum is
-    // kept exactly (a 3 w_i c_i.dj correction with dj = rho u - sum_i c_i gw_i formed in
-    // FP64), so the collision conserves momentum to FP32 rounding of small deviations and a
-    // weak body force is not lost to rounding.
+    // kept exactly: a 3 w_i c_i.dj correction with dj = rho u - sum_i c_i gw_i.  With the
+    // moments in FP64, dj is formed in FP64 from them; with the moments in FP32 (M32), as
+    // sum_i c_i d_i + F/2 from the very deviations d_i = g_i - gw_i the collision relaxes,
+    // small numbers rounded relative to themselves.  Either way the collision conserves
+    // momentum to FP32 rounding of small deviations, and a weak body force is not lost to
+    // rounding.
     const RefTerms R = ref_terms(I, phi, REFP ? cp : 0.0f, cux, cuy);
-    float gw[9];
+    float gw[9], d[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) gw[i] = geq_ref(i, R.A, R.B, cux, cuy, R.H);
-    double wx = (double)gw[1];
-    wx -= (double)gw[3];
-    wx += (double)gw[5];
-    wx -= (double)gw[6];
-    wx -= (double)gw[7];
-    wx += (double)gw[8];
-    double wy = (double)gw[2];
-    wy -= (double)gw[4];
-    wy += (double)gw[5];
-    wy += (double)gw[6];
-    wy -= (double)gw[7];
-    wy -= (double)gw[8];
-    const C cjx = C(3) * inv_tau_g * C(mx - wx), cjy = C(3) * inv_tau_g * C(my - wy);
+    for (int i = 0; i < 9; ++i) {
+        gw[i] = geq_ref(i, R.A, R.B, cux, cuy, R.H);
+        d[i] = eg[i] + (gs[i] - gw[i]);
+    }
+    C cjx, cjy;
+    if constexpr (M32) {
+        C djx = d[1];
+        djx -= d[3];
+        djx += d[5];
+        djx -= d[6];
+        djx -= d[7];
+        djx += d[8];
+        C djy = d[2];
+        djy -= d[4];
+        djy += d[5];
+        djy += d[6];
+        djy -= d[7];
+        djy -= d[8];
+        cjx = C(3) * inv_tau_g * (djx + C(0.5) * Fx);
+        cjy = C(3) * inv_tau_g * (djy + C(0.5) * Fy);
+    } else {
+        double wx = (double)gw[1];
+        wx -= (double)gw[3];
+        wx += (double)gw[5];
+        wx -= (double)gw[6];
+        wx -= (double)gw[7];
+        wx += (double)gw[8];
+        double wy = (double)gw[2];
+        wy -= (double)gw[4];
+        wy += (double)gw[5];
+        wy += (double)gw[6];
+        wy -= (double)gw[7];
+        wy -= (double)gw[8];
+        cjx = C(3) * inv_tau_g * C(mx - wx);
+        cjy = C(3) * inv_tau_g * C(my - wy);
+    }
     const C cg = C(1) - C(0.5) * inv_tau_g;
     const C keep = C(1) - inv_tau_g;
-    const C drho3 = C(3) * C(I.drho);
+    const C drho3 = C(3) * I.f_drho;
     const C pt = REFP ? C(0) : inv_tau_g * (C(3) * cp);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -685,8 +767,7 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
         const C frc = cg * w *
                       (C(3) * dotc<C>(i, Fx, Fy) +
                        drho3 * dotc<C>(i, cux, cuy) * dotc<C>(i, dpx, dpy));
-        const C d = eg[i] + (gs[i] - gw[i]);
-        go[i] = keep * d + frc + w * dotc<C>(i, cjx, cjy);
+        go[i] = keep * d[i] + frc + w * dotc<C>(i, cjx, cjy);
         if (!REFP) go[i] += (i == 0 ? w - C(1) : w) * pt;
     }
 }
@@ -748,7 +829,7 @@ __device__ __forceinline__ void step_tile(
     const S* fb = fsrc + I.off_dist;
     const S* gb = gsrc + I.off_dist;
     const int plane = (int)I.plane;
-    const C isf = SCALED ? C(I.inv_scale_f) : C(1), isg = SCALED ? C(I.inv_scale_g) : C(1);
+    const C isf = SCALED ? C(I.f_inv_scale_f) : C(1), isg = SCALED ? C(I.f_inv_scale_g) : C(1);
 
     // The loads of the tile are issued at raised wave priority (reduced formats), so a
     // block's memory requests go out ahead of other waves' arithmetic.
@@ -924,7 +1005,7 @@ __device__ __forceinline__ void step_tile(
     S* fo_b = fdst + I.off_dist;
     S* go_b = gdst + I.off_dist;
     const Rsrc rfo = rsrc_of(fo_b, pop_bytes), rgo = rsrc_of(go_b, pop_bytes);
-    const C sf = SCALED ? C(I.scale_f) : C(1), sgs = SCALED ? C(I.scale_g) : C(1);
+    const C sf = SCALED ? C(I.f_scale_f) : C(1), sgs = SCALED ? C(I.f_scale_g) : C(1);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if (!valid[k]) continue;
@@ -969,7 +1050,7 @@ __device__ __forceinline__ void step_tile(
             }
             const int me = (yl + 2) * RW + lx + 2;
             const float qx = sw[me].x * sq[me].z, qy = sw[me].x * sq[me].w;
-            node_update_ref<MODE, !PULL, QF, REFP>(I, fd, eg, gs, phi, r1[2], r2[1], r1[0], r0[1], r2[2], r2[0],
+            node_update_ref<MODE, !PULL, QF, REFP, SCALED>(I, fd, eg, gs, phi, r1[2], r2[1], r1[0], r0[1], r2[2], r2[0],
                                   r0[0], r0[2], res[k], qx, qy, fo, go, pw, mom);
             if (MODE != MODE_MOMENTS) {
 #pragma unroll
@@ -1123,7 +1204,7 @@ __global__ __launch_bounds__(BLOCK) void k_phi_plane(
     // phi_w, the first component of each node's state (3 or 4 floats)
     constexpr int NSF = state_floats<S>();
     const float* rb = REF ? msrc + I.off_mp : nullptr;
-    const C isf = C(I.inv_scale_f);
+    const C isf = C(I.f_inv_scale_f);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int yl = ly + rpg * k;
@@ -1187,7 +1268,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(const InstDev* __restrict__ inst
         const double fe = init_feq(w, ph, cu);
         if (REF) {
             const double ed = fe - w * (double)phw;
-            Store<S>::put(fb, i * plane + self, (float)ed * (float)I.scale_f);
+            Store<S>::put(fb, i * plane + self, (float)ed * I.f_scale_f);
         } else {
             Store<S>::put(fb, i * plane + self, (C)fe);
         }
@@ -1197,7 +1278,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(const InstDev* __restrict__ inst
         const double ge = rho * s_exact(i, ux, uy);   // p = 0
         if (REF) {
             const double eg = ge - (double)geq_ref(i, R.A, R.B, uxw, uyw, R.H);
-            Store<S>::put(gb, i * plane + self, (float)eg * (float)I.scale_g);
+            Store<S>::put(gb, i * plane + self, (float)eg * I.f_scale_g);
         } else {
             Store<S>::put(gb, i * plane + self, (C)ge);
         }
