@@ -111,6 +111,25 @@ def errors_outside(case, got, ref, mask):
     }
 
 
+def momentum_box(ratio, seed=3):
+    """A periodic 32 x 32 box with no interface (phi = 1: mu_phi grad phi = 0, so F = G),
+    density rho_l = ratio, a random velocity field of size 1e-3 and a uniform body force
+    G = (3e-7, -5e-7)."""
+    from paper_1710_09541_amd import cases
+    c = cases.taylor_green(n=32, nu=0.05, u0=1e-3)
+    rng = np.random.default_rng(seed)
+    c["ux0"] = c["ux0"] + 1e-4 * rng.standard_normal(c["ux0"].shape)
+    c["uy0"] = c["uy0"] + 1e-4 * rng.standard_normal(c["uy0"].shape)
+    c["rho_l"] = float(ratio)
+    c["Gx"], c["Gy"] = 3e-7, -5e-7
+    return c
+
+
+def total_momentum(m):
+    """sum(rho u) over the grid, both components."""
+    return np.array([(m["rho"] * m["ux"]).sum(), (m["rho"] * m["uy"]).sum()])
+
+
 def check_reduced(name, case, got, ref, steps, storage, fields):
     """Asserts the storage tolerance on `fields` of a reduced-format run against the oracle.
     u is held to the tolerance everywhere.  On a static drop, phi and p are held to it

@@ -13,8 +13,8 @@ import pytest
 
 from oracle import diag
 from paper_1710_09541_amd import cases, lbm
-from tests.parity import (TOL, check_reduced, errors, perturbed, report, run_hip, run_oracle,
-                          sensitivity)
+from tests.parity import (TOL, check_reduced, errors, momentum_box, perturbed, report, run_hip,
+                          run_oracle, sensitivity, total_momentum)
 
 pytestmark = pytest.mark.gpu
 
@@ -582,6 +582,39 @@ def test_sum_phi_conservation_all_storages():
             s1 = sim.reduce()["sum_phi"]
         print("[conservation] %s sum phi drift %.2e" % (storage, abs(s1 - s0) / s0), flush=True)
         assert abs(s1 - s0) / s0 <= tol
+
+
+@pytest.mark.parametrize("ratio", [1.0, 1000.0])
+def test_momentum_gain_equals_body_force(ratio):
+    """A periodic box with no interface under a uniform body force (tests/parity.momentum_box):
+    the total momentum grows by n N G, exactly in exact arithmetic (the oracle meets it to
+    round-off).
+    * FP64 to 1e-10 of the gain, FP32 to its tolerance 1e-5 of the gain: at ratio 1000 the
+      force per step is 3e-7 of a liquid population's momentum, and the collision's momentum
+      correction keeps it from being lost to rounding (measured 4e-6).
+    * FP16: the mean velocity gain n G / rho to its tolerance 1e-3 of the velocity scale (the
+      quantity that tolerance is stated on).  Its populations round to 11 bits every step,
+      relative to momenta of rho u ~ 1 per node at ratio 1000: unbiased noise of about 2e-6
+      per node and step against a force of 3e-7, which leaves the total gain off by about 2 %
+      after 200 steps there (2.5e-5 at ratio 1), i.e. 1e-6 of the velocity scale."""
+    c = momentum_box(ratio)
+    n, N = 200, c["nx"] * c["ny"]
+    G = np.array([c["Gx"], c["Gy"]])
+    expect = n * N * G
+    for storage in ("f64", "f32", "f16"):
+        with lbm.Simulation(c, storage=storage) as sim:
+            p0 = total_momentum(sim.moments())
+            sim.step(n)
+            gain = total_momentum(sim.moments()) - p0
+        rel = np.abs(gain / expect - 1)
+        mean_u = np.abs(gain - expect) / (N * c["rho_l"] * c["u_scale"])
+        print("[momentum] ratio %g %s: gain / (n N G) - 1 = %.2e, %.2e; mean velocity error / "
+              "u_scale %.1e, %.1e" % (ratio, storage, rel[0], rel[1], mean_u[0], mean_u[1]),
+              flush=True)
+        if storage == "f16":
+            assert np.all(mean_u < TOL["f16"]), mean_u
+        else:
+            assert np.all(rel < (1e-10 if storage == "f64" else TOL["f32"])), (storage, rel)
 
 
 def test_nonfinite_detected():

@@ -10,7 +10,7 @@ import pytest
 from oracle import oracle as O
 from oracle import diag
 from paper_1710_09541_amd import cases
-from tests.parity import paper_value
+from tests.parity import momentum_box, paper_value, total_momentum
 
 CS2 = 1.0 / 3.0
 RNG = np.random.default_rng(12345)
@@ -452,6 +452,23 @@ def test_taylor_green_decay():
         err.append(abs(nu_eff / 0.05 - 1))
     assert err[1] < 1e-3
     assert 3.0 < err[0] / err[1] < 4.5
+
+
+@pytest.mark.parametrize("ratio", [1.0, 1000.0])
+def test_momentum_gain_equals_body_force(ratio):
+    """In a periodic box every step adds exactly F to sum_i c_i g_i at each node: the
+    relaxation towards rho u = sum_i c_i g_i + F/2 (Eq. 22a) gives F/(2 tau_g), the forcing
+    of Eq. 20 (1 - 1/(2 tau_g)) F, and streaming only moves populations.  With F = G the
+    total momentum sum(rho u) therefore grows by n N G over n steps, here to round-off (a
+    dropped F/2 or a wrong forcing prefactor changes the rate by a factor of order 1)."""
+    c = momentum_box(ratio)
+    s = O.OracleSim(c, c["phi0"], c["ux0"], c["uy0"])
+    p0 = total_momentum(s.moments())
+    n, N = 200, c["nx"] * c["ny"]
+    s.step(n)
+    gain = total_momentum(s.moments()) - p0
+    expect = n * N * np.array([c["Gx"], c["Gy"]])
+    assert np.all(np.abs(gain / expect - 1) < 1e-10), gain / expect - 1
 
 
 def test_galilean_translation():
