@@ -5,8 +5,8 @@ workload.  The default workload is the largest single-GPU configuration: a batch
 independent static-drop / layered-Poiseuille instances of uneven size (grids uniform in
 32..512 per axis, density ratio 10/100/1000, seed 1; 19,195,714 nodes), advanced together
 in one launch per step.  The headline value is MLUPS (million lattice-node updates of both
-lattices per second) with FP32 storage; the FP64 format is timed on the same device and
-reported next to it.  Each format states its error against the FP64 CPU oracle:
+lattices per second) with FP32 storage; the FP64 and 16-bit formats are timed on the same
+device and reported next to it.  Each format states its error against the FP64 CPU oracle:
 
 * per instance, on a sample of the batch (every 16th instance) after the oracle's timed
   steps, max-norm errors of phi, u and p against the oracle run of each instance alone;
@@ -19,6 +19,8 @@ written once (168 B per lattice update in FP32, 336 in FP64, 96 with 16-bit
 populations).  The kernel's own design moves a per-node state each way instead of the phi
 plane and phi u: 12 bytes in FP32 (phi_w, u_w), 16 in FP64 (phi u) and with 16-bit
 populations (phi_w, p_w, u_w), so 168 / 320 / 104 B; that figure is reported beside it.
+HBM rates differ from one device to the next, so the line also carries what a plain 1 GiB
+device copy reaches on the same device (read + write) and the fraction of it achieved.
 
 Also timed (unless --no-extra):
 * the spinodal decomposition 1024 x 1024 (the earlier headline; phi0 = 0.5 + U[-0.01, 0.01],
@@ -353,6 +355,26 @@ def batch_accuracy(cs, storage, steps, refs, r, masks):
             "tol": tol, "within_tol": bool(ok)}
 
 
+def copy_bandwidth(reps=10):
+    """GB/s (bytes read + written) of a plain 1 GiB device-to-device copy on this GPU, timed
+    with HIP events over reps copies after three untimed ones."""
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    t1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * x.numel() * 4 * reps / (t0.elapsed_time(t1) / 1e3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def cpu_baseline(c, steps):
     """The FP64 oracle timed on this host's cores over a bounded sample of the workload."""
     from oracle.oracle import OracleSim
@@ -432,7 +454,7 @@ def main():
     log("workload %s, %d instance(s), %d nodes, storage %s" % (args.workload, len(cs), nodes,
                                                               args.storage))
     cpu_steps = args.cpu_steps if args.cpu_steps is not None else (40 if batch else 1500)
-    variants = args.variants if args.variants is not None else ("f64" if batch else "f64,f16")
+    variants = args.variants if args.variants is not None else "f64,f16"
 
     base = None
     ref = None
@@ -495,6 +517,8 @@ def main():
     per_launch_s = main_r["ms_per_step"] / 1e3
     m_bytes = method_bytes(args.storage, qf) * nodes
     achieved = m_bytes / per_launch_s / 1e9
+    copy_gbs = copy_bandwidth()
+    log("device copy: %.0f GB/s; the step reaches %.1f %% of it" % (copy_gbs, 100 * achieved / copy_gbs))
     out = {
         "metric": METRIC,
         "value": round(main_r["mlups"], 2),
@@ -522,7 +546,9 @@ def main():
                      "alg_bytes_per_launch": m_bytes,
                      "design_bytes_per_lu": main_r["alg_bytes_per_lu"],
                      "design_frac": round(main_r["frac_hbm_peak"], 4),
-                     "launch_us": round(per_launch_s * 1e6, 3)},
+                     "launch_us": round(per_launch_s * 1e6, 3),
+                     "copy_gbs": round(copy_gbs, 1),
+                     "frac_of_copy": round(achieved / copy_gbs, 4)},
         "cpu_baseline": base,
         "host_round_trip": trip,
         "variants": results,
