@@ -83,8 +83,8 @@ enum { LBM_LATTICE_D2Q9 = 9, LBM_LATTICE_D2Q5 = 5 };
  * half holding rest deviations (f_i - w_i phi_w) 2^exp_f, phi_w the order parameter of the
  * node that wrote the slot, and deviations of g_i from the flow equilibrium (Eq. 16) of that
  * node's published phi_w, u_w (and, F16 only, p_w), times 2^exp_g; those published values
- * are kept per node in FP32 (12 bytes per node in F32, 16 in F16).  Arithmetic in FP32,
- * with phi-to-rho and the velocity and pressure moments (Eqs. 13, 22) in FP64. */
+ * are kept per node in FP32 (12 bytes per node in F32, 16 in F16).  Arithmetic in FP32;
+ * F32 forms phi-to-rho and the velocity and pressure moments (Eqs. 13, 22) in FP64. */
 enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16 = 2 };
 
 /* population stores of the step: AUTO lets the autotuner choose; CACHED are ordinary

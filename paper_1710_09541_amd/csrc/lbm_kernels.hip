@@ -6,7 +6,7 @@
 // [plane i][y][pitch], x fastest.  A step pulls f_i(x - c_i), g_i(x - c_i) (streaming with
 // the boundary rules), recomputes phi on the tile and a one-node halo into LDS, evaluates
 // the isotropic stencils (Eqs. 27-28), the local closure (Eqs. 2-3, 5-7, 13, 19, 23-26),
-// the FP64 moments u then p (Eq. 22), the backward difference of phi u (Eq. 11), collides
+// the moments u then p (Eq. 22), the backward difference of phi u (Eq. 11), collides
 // both lattices (Eqs. 8-9, 11, 15-17, 20) and writes the result at the node itself into the
 // other buffer.  The very first step reads the initial (already streamed) distributions
 // in place instead of pulling.
@@ -19,7 +19,8 @@
 // decodes a pulled population with the (phi_w, p_w, u_w) of its source node,
 // staged with a two-node halo in LDS; the g equilibrium is evaluated by one function,
 // identically on both sides.  The moments, and the momentum the g relaxation must keep,
-// are formed in FP64.  The stored numbers are thus the small
+// are formed in FP64 (FP32 format) or from the FP32 deviations themselves (16-bit format).
+// The stored numbers are thus the small
 // non-equilibrium parts, a bulk at rest is stored exactly, and the short formats round
 // small values only: slowly varying states keep their small increments (a weak body
 // force, a drifting interface) instead of losing them to the rounding of full-size
@@ -508,9 +509,10 @@ __device__ __forceinline__ float geq_ref(int i, float A, float B, float ux, floa
 }
 
 // f: e_i = f_i - w_i phi of the arriving populations; eg, gs: the arriving g_i as stored
-// deviation and reference equilibrium of its source node (g_i = eg_i + gs_i, summed in
-// FP64 for the moments); phi and its 8 neighbours; res: rounding error of phi (the f
-// populations sum to phi + res); qx, qy: phi_w u_w of this node at the previous step.
+// deviation and reference equilibrium of its source node (g_i = eg_i + gs_i, summed for
+// the moments in FP64, or in FP32 with M32); phi and its 8 neighbours; res: rounding error
+// of phi (the f populations sum to phi + res); qx, qy: phi_w u_w of this node at the
+// previous step.
 // Writes the collided e_i into fo, the g deviations g*_i - g^eq_i(published moments) into
 // go and the published p_w, u_w into pw, or the moments into mom.  FIRST: the state is the
 // initial one, f = f^eq(phi0, u0) and g = g^eq(p = 0, u0) at every node.  REFP: the g
