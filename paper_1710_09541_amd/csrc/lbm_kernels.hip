@@ -693,17 +693,19 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
     // before and after the collision (sum f^eq = phi, sum F_i = 0); the rest population is
     // taken from that invariant, so neither the rounding of phi nor the inexact FP32 weights
     // can bias the total phi.
+    // With f^eq_i - w_i phi = 3 w_i phi c_i.u (Eq. 9) and the source F_i = (1 - 1/(2 tau_phi))
+    // w_i c_i.a, a = 3 D + lambda n (Eq. 11), the update e_i - (e_i - (f^eq_i - w_i phi)) /
+    // tau_phi + F_i is e_i (1 - 1/tau_phi) + w_i c_i.v with one vector
+    // v = 3 phi u / tau_phi + (1 - 1/(2 tau_phi)) a per node.
     const C itf = I.f_inv_tau_f, cf = I.f_cf;
     const C ax = C(3) * Dx + lam * nx_;
     const C ay = C(3) * Dy + lam * ny_;
-    const C phi3 = C(3) * phi;
+    const C phi3t = C(3) * phi * itf;
+    const C vx = phi3t * cux + cf * ax;
+    const C vy = phi3t * cuy + cf * ay;
+    const C keepf = C(1) - itf;
 #pragma unroll
-    for (int i = 1; i < QF; ++i) {
-        const C w = wf<C, QF>(i);
-        const C feq = w * phi3 * dotc<C>(i, cux, cuy);
-        const C src = cf * w * dotc<C>(i, ax, ay);
-        fo[i] = f[i] - (f[i] - feq) * itf + src;
-    }
+    for (int i = 1; i < QF; ++i) fo[i] = f[i] * keepf + wf<C, QF>(i) * dotc<C>(i, vx, vy);
     C t = fo[1];
 #pragma unroll
     for (int i = 2; i < QF; ++i) t += fo[i];
@@ -759,18 +761,21 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
         cjx = C(3) * inv_tau_g * C(mx - wx);
         cjy = C(3) * inv_tau_g * C(my - wy);
     }
-    const C cg = C(1) - C(0.5) * inv_tau_g;
+    // G_i (Eq. 20) = w_i [c_i.(3 cg F) + 3 cg (rho_l - rho_g) (c_i.u)(c_i.grad phi)] with
+    // cg = 1 - 1/(2 tau_g); its c_i-linear part and the momentum correction share one vector
+    // e = 3 cg F + cj, and the pressure part (REFP false) is w_i pt for i != 0.
+    const C cg3 = C(3) - C(1.5) * inv_tau_g;
     const C keep = C(1) - inv_tau_g;
-    const C drho3 = C(3) * I.f_drho;
+    const C bq = cg3 * I.f_drho;
+    const C ex = cg3 * Fx + cjx, ey = cg3 * Fy + cjy;
     const C pt = REFP ? C(0) : inv_tau_g * (C(3) * cp);
+    go[0] = keep * d[0];
+    if (!REFP) go[0] += (wgt<C>(0) - C(1)) * pt;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const C w = wgt<C>(i);
-        const C frc = cg * w *
-                      (C(3) * dotc<C>(i, Fx, Fy) +
-                       drho3 * dotc<C>(i, cux, cuy) * dotc<C>(i, dpx, dpy));
-        go[i] = keep * d[i] + frc + w * dotc<C>(i, cjx, cjy);
-        if (!REFP) go[i] += (i == 0 ? w - C(1) : w) * pt;
+    for (int i = 1; i < 9; ++i) {
+        C t = dotc<C>(i, ex, ey) + bq * dotc<C>(i, cux, cuy) * dotc<C>(i, dpx, dpy);
+        if (!REFP) t += pt;
+        go[i] = keep * d[i] + wgt<C>(i) * t;
     }
 }
 
