@@ -174,6 +174,22 @@ def test_impact_full_size_spreading_reduced_vs_fp64(Re):
         assert abs(C_early / paper_value("spreading_prefactor_C") - 1) < 0.1
 
 
+@pytest.mark.parametrize("Re", [20.0, 100.0, 500.0])
+def test_impact_full_size_f64_bitwise_equal_to_oracle(Re):
+    """The impact at its full size (2048 x 512, D = 256, open top) in the autotuned launch:
+    the FP64 format equals the oracle bit for bit on every field after 300 steps, the drop
+    already deforming against the film."""
+    c = cases.droplet_impact(2048, 512, D=256, Re=Re)
+    ref = run_oracle(c, 300)
+    with lbm.Simulation(c, storage="f64", kernel="auto", stores="auto") as sim:
+        sim.step(300)
+        got = sim.moments()
+        info = sim.info()
+    for k in ref:
+        assert np.array_equal(got[k], ref[k]), (Re, k, info)
+    print("[bitwise] impact 2048x512 Re %g f64 300 steps (%s): equal" % (Re, info), flush=True)
+
+
 def test_impact_full_size_re500():
     """The impact as specified at Re = 500 (2048 x 512, D = 256, film 0.1 D, nu_l = 0.0256,
     tau_l = 0.577).  FP32 and FP16 storage track the FP64 format's spreading radius within
