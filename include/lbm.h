@@ -244,8 +244,10 @@ int lbm_reduce(lbm_ctx* c, int32_t inst, const double* mask, lbm_diag* out);
  * caller.  Synchronises the context's stream. */
 int lbm_reduce_noalloc(lbm_ctx* c, int32_t inst, const double* mask, lbm_diag* out);
 
-/* Serialises the complete state (distributions, phi u of the previous step, step count).
- * With buf == NULL only *bytes is set to the size needed.  Synchronises. */
+/* Serialises the complete state: a versioned header, both lattices' distributions, the
+ * per-node state that carries phi u of the previous step (FP64: phi u; F32 / F16: the
+ * published phi_w, u_w and, F16, p_w) with the pressure of the edge rows of open sides, and
+ * the step count.  With buf == NULL only *bytes is set to the size needed.  Synchronises. */
 int lbm_get_state(lbm_ctx* c, void* buf, size_t* bytes);
 
 /* Restores a state written by lbm_get_state of a context with the same storage format,
