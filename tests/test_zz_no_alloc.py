@@ -7,7 +7,7 @@ from paper_1710_09541_amd import cases, lbm
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16"])
 def test_noalloc_reduce_equals_lbm_reduce_on_two_calls(storage):
     """Two calls in a row, the second on a smaller instance (the scratch keeps the first
     call's larger planes), then the first again and a second context on the same GPU: every
