@@ -839,16 +839,24 @@ __device__ __forceinline__ void step_tile(
     const C isf = SCALED ? C(I.f_inv_scale_f) : C(1), isg = SCALED ? C(I.f_inv_scale_g) : C(1);
 
     // The loads of the tile are issued at raised wave priority (reduced formats), so a
-    // block's memory requests go out ahead of other waves' arithmetic.
+    // block's memory requests go out ahead of other waves' arithmetic.  Every load of the
+    // tile (the staged previous state, the node's populations, the ring's) is issued before
+    // the first wait, so a block spends one memory round trip, not one per staging pass.
     if (REF) __builtin_amdgcn_s_setprio(3);
-    // previous planes over the tile and a two-node halo (wrapped; clamped rows beyond a
-    // wall or an open side are never sources)
+    // previous per-node state over the tile and a two-node halo (wrapped; clamped rows
+    // beyond a wall or an open side are never sources), NIT entries per thread
+    constexpr int NIT = (NR + BLOCK - 1) / BLOCK;
+    float4 m4[REF && REFP ? NIT : 1];
+    float3 m3[REF && !REFP ? NIT : 1];
     if (REF) {
         const float* mb = msrc + I.off_mp;
         const bool pery = I.bc_lo == BC_PERIODIC;
         // one wrap suffices when the grid is at least as wide / tall as the staged block
         const bool wide = nx >= RW, tall = ny >= TY + 4;
-        for (int idx = tid; idx < NR; idx += BLOCK) {
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int idx = tid + it * BLOCK;
+            if (idx >= NR) break;
             const int sy = idx / RW - 2, sx = idx - (idx / RW) * RW - 2;
             int gx = T.x0 + sx;
             if (INTERIOR) {
@@ -868,23 +876,8 @@ __device__ __forceinline__ void step_tile(
                 gy %= ny;
                 gy = gy < 0 ? gy + ny : gy;
             }
-            float ph, pp, ux, uy;
-            if constexpr (REFP) {
-                const float4 m4 = ld((const float4*)mb, gy * pitch + gx);
-                ph = m4.x;
-                pp = m4.y;
-                ux = m4.z;
-                uy = m4.w;
-            } else {
-                const float3 m3 = ld((const float3*)mb, gy * pitch + gx);
-                ph = m3.x;
-                pp = 0.0f;
-                ux = m3.y;
-                uy = m3.z;
-            }
-            const RefTerms R = ref_terms(I, ph, pp, ux, uy);
-            sq[idx] = make_float4(R.A, R.B, R.ux, R.uy);
-            sw[idx] = make_float2(ph, R.H);
+            if constexpr (REFP) m4[it] = ld((const float4*)mb, gy * pitch + gx);
+            else m3[it] = ld((const float3*)mb, gy * pitch + gx);
         }
     }
 
@@ -963,7 +956,28 @@ __device__ __forceinline__ void step_tile(
             }
         }
     }
+    // the staged state's decode terms, into LDS
     if (REF) {
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int idx = tid + it * BLOCK;
+            if (idx >= NR) break;
+            float ph, pp, ux, uy;
+            if constexpr (REFP) {
+                ph = m4[it].x;
+                pp = m4[it].y;
+                ux = m4[it].z;
+                uy = m4[it].w;
+            } else {
+                ph = m3[it].x;
+                pp = 0.0f;
+                ux = m3[it].y;
+                uy = m3[it].z;
+            }
+            const RefTerms R = ref_terms(I, ph, pp, ux, uy);
+            sq[idx] = make_float4(R.A, R.B, R.ux, R.uy);
+            sw[idx] = make_float2(ph, R.H);
+        }
         __builtin_amdgcn_s_setprio(0);
         __syncthreads();
     }
