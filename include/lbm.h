@@ -116,6 +116,15 @@ enum { LBM_STRIP_AUTO = 0, LBM_STRIP_ROWS = -1 };   /* or a strip width of 8 or 
  * autotuner time both where they differ.  Results are bitwise identical either way. */
 enum { LBM_NARROW_AUTO = 0, LBM_NARROW_OFF = -1, LBM_NARROW_ON = 1 };
 
+/* How the step's tiles are dealt to the 8 XCDs of MI355X (each with its own L2), one block
+ * per tile.  BANDS: each XCD takes one contiguous eighth of the tile list, so it finds the
+ * halo rows of its previous tiles in its own L2: the best order for one large grid.  A chunk
+ * of n tiles (1 to 4096): the XCDs take chunks of n consecutive tiles in turn, which evens
+ * out their work when tile costs vary along the list (a batch of instances of different
+ * shapes).  AUTO lets the autotuner time bands against chunks of 16 tiles.  A persistent
+ * grid always runs bands.  Results are bitwise identical either way. */
+enum { LBM_DEAL_AUTO = 0, LBM_DEAL_BANDS = -1 };
+
 /* kernel choice for the step */
 enum {
     LBM_KERNEL_AUTO = 0,  /* the autotuner picks */
@@ -163,6 +172,8 @@ typedef struct {
     int32_t grid;             /* LBM_GRID_* (AUTO: one block per tile) */
     int32_t strip;            /* LBM_STRIP_AUTO (timed at lbm_init), LBM_STRIP_ROWS, 8 or 16 */
     int32_t narrow_tiles;     /* LBM_NARROW_AUTO (timed at lbm_init), LBM_NARROW_OFF or _ON */
+    int32_t deal;             /* LBM_DEAL_AUTO (timed at lbm_init), LBM_DEAL_BANDS or a chunk
+                                 of 1 to 4096 tiles */
 } lbm_options;
 
 /* Integral diagnostics of one instance, FP64 accumulation in a fixed order, over the
@@ -259,10 +270,13 @@ int lbm_set_state(lbm_ctx* c, const void* buf, size_t bytes);
 
 /* Number of steps taken; the kernel (LBM_KERNEL_FUSED / SPLIT), tile rows, population
  * stores (LBM_STORES_CACHED / STREAMING), launch grid (LBM_GRID_TILES / PERSISTENT), tile
- * order (LBM_STRIP_ROWS, 8 or 16) and narrow tiles (LBM_NARROW_ON / OFF) the context runs
- * with.  Any pointer may be NULL; LBM_ERR_PARAM if c is NULL. */
+ * order (LBM_STRIP_ROWS, 8 or 16), narrow tiles (LBM_NARROW_ON / OFF) and dealing of the
+ * tiles to the XCDs (LBM_DEAL_BANDS, or the chunk in tiles) the context runs with.  A chunk
+ * at least as long as an XCD's band is reported as LBM_DEAL_BANDS, which it then is.  Any
+ * pointer may be NULL; LBM_ERR_PARAM if c is NULL. */
 int lbm_info(const lbm_ctx* c, int64_t* step, int32_t* kernel, int32_t* tile_rows,
-             int32_t* stores, int32_t* grid, int32_t* strip, int32_t* narrow_tiles);
+             int32_t* stores, int32_t* grid, int32_t* strip, int32_t* narrow_tiles,
+             int32_t* deal);
 
 /* Build provenance: the sha256 (64 hex digits) of the source files the library was built
  * from, fixed at compile time; the Python binding compares it with the sources beside the

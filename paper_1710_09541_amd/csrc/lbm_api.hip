@@ -43,7 +43,13 @@ constexpr int NGRAPH = 3;
 constexpr int NSTRIP = 3;
 constexpr int STRIP_TILES[NSTRIP] = {0, 8, 16};
 constexpr int GRAPH_STEPS[NGRAPH] = {2, 16, 64};
-constexpr int PLANE_PAD = 192;  // elements added to each plane: breaks power-of-two plane strides
+constexpr int PLANE_PAD = 192;
+// tiles per chunk when the tiles are dealt to the XCDs in chunks: the longest accepted, and
+// the one the autotuner times against one band per XCD (measured on a batch of 256 ragged
+// instances, FP32: chunks of 4, 8, 16 and 64 tiles +8.5, +9.6, +10.2 and +7.6 % over bands;
+// on single grids of 1024^2 and 4096^2 bands win by 4 to 12 %)
+constexpr int MAX_CHUNK = 4096;
+constexpr int AUTO_CHUNK = 16;  // elements added to each plane: breaks power-of-two plane strides
 
 // Device scratch of lbm_reduce_noalloc, for callers that cannot allocate: the five FP64
 // moment planes of one instance of at most NOALLOC_MAX_NODES nodes, then the reduction's
@@ -109,6 +115,7 @@ struct lbm_ctx {
     TileList lists[3][NSTRIP][2];
     int strip = 0;             // tile order in use (index into STRIP_TILES)
     int narrow = 0;            // 1: narrow tiles at the right end of ragged instances
+    int chunk = 0;             // tiles per chunk dealt to an XCD in turn; 0: one band per XCD
     double* mom = nullptr;     // 5 * max nodes, moments scratch
     double* partials = nullptr;
     double* red_out = nullptr;
@@ -417,6 +424,7 @@ StepArgs step_args(lbm_ctx* c, int src, bool pull, int rows, bool split, void* q
     a.qf = c->qf;
     a.nt_store = false;
     a.persist = 0;
+    a.chunk = 0;
     a.pull = pull;
     a.split = split;
     a.fsrc = c->f[src];
@@ -441,6 +449,7 @@ int launch_one(lbm_ctx* c, hipStream_t st) {
                       c->strip, c->narrow);
         a.nt_store = c->nt_store;
         a.persist = runs_persistent(c) ? persist_blocks(c, c->tile_rows, c->nt_store) : 0;
+        a.chunk = c->chunk;
     }
     a.stream = st;
     hipError_t e = launch_step(c->storage, a);
@@ -548,9 +557,10 @@ int check_finite(lbm_ctx* c) {
 // ------------------------------------------------------------------ autotuner cache
 // If the environment variable LBM_AUTOTUNE_CACHE names a file, tuned choices are kept there,
 // one text line per configuration:
-//   lbm-tune-v4 <key> <kernel> <tile_rows> <streaming stores 0/1> <persistent grid 0/1>
+//   lbm-tune-v5 <key> <kernel> <tile_rows> <streaming stores 0/1> <persistent grid 0/1>
 //               <tile order 0/1/2: whole rows, strips of 8, strips of 16 tiles>
 //               <narrow tiles at the right end of ragged instances 0/1>
+//               <tiles per chunk dealt to the XCDs, 0: one band per XCD>
 // The key covers everything the timing depends on: the GPU architecture, storage, phase-
 // field lattice, the requested kernel / tile rows / store policy / grid / order, the number of
 // instances and every instance's grid size.  A missing, unreadable or malformed file only means the
@@ -566,7 +576,7 @@ std::string tune_key(const lbm_ctx* c) {
         if (ch == ' ') ch = '_';
     k << arch << ":s" << c->storage << ":q" << c->qf << ":k" << c->opt.kernel << ":r"
       << c->opt.tile_rows << ":w" << c->opt.stores << ":g" << c->opt.grid << ":o" << c->opt.strip
-      << ":t" << c->opt.narrow_tiles << ":n" << c->inst.size();
+      << ":t" << c->opt.narrow_tiles << ":d" << c->opt.deal << ":n" << c->inst.size();
     for (const Instance& I : c->inst) k << ":" << I.p.nx << "x" << I.p.ny;
     return k.str();
 }
@@ -580,16 +590,17 @@ bool tune_cache_lookup(lbm_ctx* c, const std::string& key) {
     while (std::getline(in, line)) {
         std::istringstream ls(line);
         std::string tag, k;
-        int kernel = 0, rows = 0, nt = 0, pg = 0, si = 0, nw = 0;
-        if (!(ls >> tag >> k >> kernel >> rows >> nt >> pg >> si >> nw) ||
-            tag != "lbm-tune-v4" || k != key)
+        int kernel = 0, rows = 0, nt = 0, pg = 0, si = 0, nw = 0, ch = 0;
+        if (!(ls >> tag >> k >> kernel >> rows >> nt >> pg >> si >> nw >> ch) ||
+            tag != "lbm-tune-v5" || k != key)
             continue;
         if ((kernel != LBM_KERNEL_FUSED && kernel != LBM_KERNEL_SPLIT) || list_index(rows) < 0 ||
             (nt != 0 && nt != 1) || (pg != 0 && pg != 1) || si < 0 || si >= NSTRIP ||
-            (nw != 0 && nw != 1))
+            (nw != 0 && nw != 1) || ch < 0 || ch > MAX_CHUNK)
             continue;
         c->strip = si;
         c->narrow = nw;
+        c->chunk = ch;
         c->kernel = kernel;   // the last valid line for the key wins
         c->tile_rows = rows;
         c->nt_store = nt == 1;
@@ -603,9 +614,9 @@ void tune_cache_store(const lbm_ctx* c, const std::string& key) {
     const char* path = getenv("LBM_AUTOTUNE_CACHE");
     if (!path || !*path) return;
     std::ofstream out(path, std::ios::app);
-    if (out) out << "lbm-tune-v4 " << key << " " << c->kernel << " " << c->tile_rows << " "
+    if (out) out << "lbm-tune-v5 " << key << " " << c->kernel << " " << c->tile_rows << " "
                  << (c->nt_store ? 1 : 0) << " " << (c->persistent ? 1 : 0) << " " << c->strip
-                 << " " << c->narrow << "\n";
+                 << " " << c->narrow << " " << c->chunk << "\n";
 }
 
 // ------------------------------------------------------------------ autotuner
@@ -622,7 +633,7 @@ int autotune(lbm_ctx* c) {
     struct Cand {
         int kernel, rows;
         bool nt, persistent;
-        int strip, narrow;
+        int strip, narrow, chunk;
     };
     std::vector<Cand> cands;
     const bool want_fused = c->opt.kernel != LBM_KERNEL_SPLIT;
@@ -657,6 +668,13 @@ int autotune(lbm_ctx* c) {
         narrows = {1, 0};
     else
         narrows.push_back(0);
+    // dealing of the tiles to the XCDs: the requested one, or one band per XCD and then
+    // chunks of AUTO_CHUNK tiles where a band is longer than that
+    std::vector<int> chunks;
+    if (c->opt.deal != LBM_DEAL_AUTO)
+        chunks.push_back(c->chunk);
+    else
+        chunks = {0, AUTO_CHUNK};
     const int rows_opts[3] = {4, 8, 16};
     for (int r : rows_opts) {
         if (c->opt.tile_rows && c->opt.tile_rows != r) continue;
@@ -667,13 +685,20 @@ int autotune(lbm_ctx* c) {
             for (int pg = 0; pg < 2; ++pg) {
                 if ((pg && !want_persistent) || (!pg && !want_tiles)) continue;
                 for (int si : strips)
-                    for (int nw : narrows) {
-                        if (want_fused)
-                            cands.push_back({LBM_KERNEL_FUSED, r, nt == 1, pg == 1, si, nw});
-                        // the split kernel runs one block per tile
-                        if (want_split && !pg)
-                            cands.push_back({LBM_KERNEL_SPLIT, r, nt == 1, false, si, nw});
-                    }
+                    for (int nw : narrows)
+                        for (int ch : chunks) {
+                            // a persistent grid runs one band per XCD; a chunk at least as
+                            // long as the band is the band
+                            const int per =
+                                (c->lists[list_index(r)][si][nw].count + NXCD - 1) / NXCD;
+                            if (ch != chunks[0] && (pg || ch >= per)) continue;
+                            if (want_fused)
+                                cands.push_back({LBM_KERNEL_FUSED, r, nt == 1, pg == 1, si, nw,
+                                                 pg ? 0 : ch});
+                            // the split kernel runs one block per tile
+                            if (want_split && !pg)
+                                cands.push_back({LBM_KERNEL_SPLIT, r, nt == 1, false, si, nw, ch});
+                        }
             }
         }
     }
@@ -684,6 +709,7 @@ int autotune(lbm_ctx* c) {
         c->persistent = cands[0].persistent;
         c->strip = cands[0].strip;
         c->narrow = cands[0].narrow;
+        c->chunk = cands[0].chunk;
         return LBM_OK;
     }
     HIPCHK(c, copy_n_async(c->q_tune, c->q, c->q_elems * sizeof(double), c->stream));
@@ -732,6 +758,7 @@ int autotune(lbm_ctx* c) {
                       cd.strip, cd.narrow);
         a.nt_store = cd.nt;
         a.persist = cd.persistent ? persist_blocks(c, cd.rows, cd.nt) : 0;
+        a.chunk = cd.chunk;
         b = a;
         if (alt) {
             // temporary -> spare, then spare -> temporary
@@ -784,6 +811,7 @@ int autotune(lbm_ctx* c) {
                 c->persistent = cands[ci].persistent;
                 c->strip = cands[ci].strip;
                 c->narrow = cands[ci].narrow;
+                c->chunk = cands[ci].chunk;
             }
         }
     }
@@ -824,6 +852,8 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
     if (o.narrow_tiles != LBM_NARROW_AUTO && o.narrow_tiles != LBM_NARROW_OFF &&
         o.narrow_tiles != LBM_NARROW_ON)
         return fail(nullptr, LBM_ERR_PARAM, "narrow_tiles must be 0 (auto), -1 (off) or 1 (on)");
+    if (o.deal != LBM_DEAL_AUTO && o.deal != LBM_DEAL_BANDS && (o.deal < 1 || o.deal > MAX_CHUNK))
+        return fail(nullptr, LBM_ERR_PARAM, "deal must be 0 (auto), -1 (bands) or 1 to 4096 tiles");
     const auto lattice_of = [](const lbm_params& q) {
         return q.f_lattice == 0 ? (int)LBM_LATTICE_D2Q9 : (int)q.f_lattice;
     };
@@ -998,6 +1028,7 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
     c->persistent = o.grid == LBM_GRID_PERSISTENT;
     c->strip = o.strip == 8 ? 1 : (o.strip == 16 ? 2 : 0);
     c->narrow = o.narrow_tiles == LBM_NARROW_ON ? 1 : 0;
+    c->chunk = o.deal > 0 ? o.deal : 0;
     {
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -1013,7 +1044,7 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
     }
     if (o.kernel == LBM_KERNEL_AUTO || o.tile_rows == 0 || o.stores == LBM_STORES_AUTO ||
         o.grid == LBM_GRID_AUTO || o.strip == LBM_STRIP_AUTO ||
-        o.narrow_tiles == LBM_NARROW_AUTO) {
+        o.narrow_tiles == LBM_NARROW_AUTO || o.deal == LBM_DEAL_AUTO) {
         const std::string key = tune_key(c);
         if (!tune_cache_lookup(c, key)) {
             int rc = autotune(c);
@@ -1220,7 +1251,8 @@ int lbm_set_state(lbm_ctx* c, const void* buf, size_t bytes) {
 }
 
 int lbm_info(const lbm_ctx* c, int64_t* step, int32_t* kernel, int32_t* tile_rows,
-             int32_t* stores, int32_t* grid, int32_t* strip, int32_t* narrow_tiles) {
+             int32_t* stores, int32_t* grid, int32_t* strip, int32_t* narrow_tiles,
+             int32_t* deal) {
     if (!c) return fail(nullptr, LBM_ERR_PARAM, "context is NULL");
     if (step) *step = c->step;
     if (kernel) *kernel = c->kernel;
@@ -1229,6 +1261,13 @@ int lbm_info(const lbm_ctx* c, int64_t* step, int32_t* kernel, int32_t* tile_row
     if (grid) *grid = runs_persistent(c) ? LBM_GRID_PERSISTENT : LBM_GRID_TILES;
     if (strip) *strip = c->strip == 0 ? LBM_STRIP_ROWS : STRIP_TILES[c->strip];
     if (narrow_tiles) *narrow_tiles = c->narrow ? LBM_NARROW_ON : LBM_NARROW_OFF;
+    if (deal) {
+        // what the steps run with: a chunk shorter than an XCD's band, else one band per XCD
+        const int per =
+            (c->lists[list_index(c->tile_rows)][c->strip][c->narrow].count + NXCD - 1) / NXCD;
+        *deal = (c->chunk > 0 && c->chunk < per && !runs_persistent(c)) ? c->chunk
+                                                                          : LBM_DEAL_BANDS;
+    }
     return LBM_OK;
 }
 

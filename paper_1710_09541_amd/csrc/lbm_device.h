@@ -67,6 +67,8 @@ struct StepArgs {
     bool nt_store;      // non-temporal population stores
     int persist;        // > 0: persistent grid of that many blocks per XCD, each looping over
                         // tiles; 0: one block per tile
+    int chunk;          // one block per tile: the tiles go to the XCDs in chunks of this
+                        // many consecutive tiles, in turn; 0: one contiguous band per XCD
     const void* fsrc;
     const void* gsrc;
     void* fdst;

@@ -787,11 +787,16 @@ __device__ __forceinline__ void node_update_ref(const InstDev& I, const float (&
 // formats the block first stages the previous step's per-node state (phi_w, u_w and, 16-bit
 // format, p_w) over the tile plus two nodes into LDS, to decode the pulled populations.
 //
-// Block b runs tile (b % 8) * per_xcd + b / 8: the hardware deals blocks round-robin to
-// the 8 XCDs, so each XCD walks one contiguous run of tiles and finds the halo rows of
-// its previous tiles in its own L2.  With a persistent grid (stride < per_xcd blocks per
-// XCD, as many as stay resident) block b then moves on to every stride-th tile of the same
-// run, with a barrier between tiles so the next tile's LDS writes wait for this one's reads.
+// The hardware deals blocks round-robin to the 8 XCDs, so block b runs on XCD b % 8 as that
+// XCD's (b / 8)-th block.  The tile list is handed to the XCDs in chunks of `chunk`
+// consecutive tiles, chunk after chunk in turn: XCD x takes chunks x, x + 8, x + 16, ...  An
+// XCD thus walks runs of neighbouring tiles and finds the halo rows of its previous tiles in
+// its own L2.  One chunk per XCD (chunk = ntiles / 8 rounded up) gives each XCD one
+// contiguous band, the best order for a single large grid; shorter chunks even out the
+// work of the dies when the tiles' costs vary along the list (a batch of instances of
+// different shapes).  With a persistent grid (stride < chunk blocks per XCD, as many as stay
+// resident; one band per XCD) block b then moves on to every stride-th tile of its band, with
+// a barrier between tiles so the next tile's LDS writes wait for this one's reads.
 //
 // RING_FROM_PLANE (split step): the halo ring is read from a phi plane written by
 // k_phi_plane instead of being recomputed.
@@ -1148,7 +1153,7 @@ template <typename S, int K, bool PULL, int MODE, bool RING_FROM_PLANE, int QF,
           bool PERSIST = false>
 __global__ __launch_bounds__(BLOCK) void k_step(
     const InstDev* __restrict__ insts, const TileDesc* __restrict__ tiles, int ntiles,
-    int per_xcd, int stride, const S* __restrict__ fsrc, const S* __restrict__ gsrc, S* __restrict__ fdst,
+    int chunk, int stride, const S* __restrict__ fsrc, const S* __restrict__ gsrc, S* __restrict__ fdst,
     S* __restrict__ gdst, double* __restrict__ q,
     const typename Store<S>::C* __restrict__ phiplane, const float* __restrict__ msrc,
     float* __restrict__ mdst, double* __restrict__ mom_out) {
@@ -1187,15 +1192,16 @@ __global__ __launch_bounds__(BLOCK) void k_step(
     if constexpr (!PERSIST) {
         // one tile per block (a loop here, even of one pass, costs the compiler 15 to 35
         // more registers)
-        const int t = (b % NXCD) * per_xcd + b / NXCD;
+        const int xcd = b % NXCD, j = b / NXCD, jc = j / chunk;
+        const int t = (jc * NXCD + xcd) * chunk + (j - jc * chunk);
         if (t < ntiles) run(t);
     } else {
         const int xcd = b % NXCD;
-        for (int j = b / NXCD; j < per_xcd; j += stride) {
-            const int t = xcd * per_xcd + j;
+        for (int j = b / NXCD; j < chunk; j += stride) {
+            const int t = xcd * chunk + j;
             if (t >= ntiles) return;
             run(t);
-            if (j + stride < per_xcd) __syncthreads();
+            if (j + stride < chunk) __syncthreads();
         }
     }
 }
@@ -1321,11 +1327,26 @@ inline int grid_for(int ntiles, int& per_xcd) {
     return per_xcd * NXCD;
 }
 
+// one block per tile, the tiles dealt to the XCDs in chunks of `chunk` (0 or at least
+// ntiles / 8: one band per XCD); returns the grid and sets the chunk the kernel takes
+inline int grid_dealt(int ntiles, int chunk, int& ch) {
+    int per;
+    const int g = grid_for(ntiles, per);
+    if (chunk <= 0 || chunk >= per) {
+        ch = per;
+        return g;
+    }
+    ch = chunk;
+    return (ntiles + NXCD * chunk - 1) / (NXCD * chunk) * (NXCD * chunk);
+}
+
 template <typename S, int K, int QF>
 hipError_t step_k(const StepArgs& a) {
     using C = typename Store<S>::C;
     int per;
-    const int tile_grid = grid_for(a.ntiles, per);  // one block per tile
+    const int tile_grid = grid_for(a.ntiles, per);  // one block per tile, a band per XCD
+    int ch;
+    const int dealt_grid = grid_dealt(a.ntiles, a.chunk, ch);  // one block per tile, dealt
     // persistent grid (fused pull step only): a.persist blocks per XCD, each looping over
     // that XCD's tiles
     int stride = per;
@@ -1346,11 +1367,11 @@ hipError_t step_k(const StepArgs& a) {
         k_phi_plane<S, K, QF><<<tile_grid, BLOCK, 0, a.stream>>>(a.insts, a.tiles, a.ntiles, per,
                                                                  fs, rs, ph);
         if (a.nt_store)
-            k_step<S, K, true, MODE_STEP_NT, true, QF><<<tile_grid, BLOCK, 0, a.stream>>>(
-                a.insts, a.tiles, a.ntiles, per, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
+            k_step<S, K, true, MODE_STEP_NT, true, QF><<<dealt_grid, BLOCK, 0, a.stream>>>(
+                a.insts, a.tiles, a.ntiles, ch, ch, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
         else
-            k_step<S, K, true, MODE_STEP, true, QF><<<tile_grid, BLOCK, 0, a.stream>>>(
-                a.insts, a.tiles, a.ntiles, per, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
+            k_step<S, K, true, MODE_STEP, true, QF><<<dealt_grid, BLOCK, 0, a.stream>>>(
+                a.insts, a.tiles, a.ntiles, ch, ch, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
     } else if (stride < per) {
         // fused step on a persistent grid
         if (a.nt_store)
@@ -1360,11 +1381,11 @@ hipError_t step_k(const StepArgs& a) {
             k_step<S, K, true, MODE_STEP, false, QF, true><<<grid, BLOCK, 0, a.stream>>>(
                 a.insts, a.tiles, a.ntiles, per, stride, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
     } else if (a.nt_store) {
-        k_step<S, K, true, MODE_STEP_NT, false, QF><<<tile_grid, BLOCK, 0, a.stream>>>(
-            a.insts, a.tiles, a.ntiles, per, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
+        k_step<S, K, true, MODE_STEP_NT, false, QF><<<dealt_grid, BLOCK, 0, a.stream>>>(
+            a.insts, a.tiles, a.ntiles, ch, ch, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
     } else {
-        k_step<S, K, true, MODE_STEP, false, QF><<<tile_grid, BLOCK, 0, a.stream>>>(
-            a.insts, a.tiles, a.ntiles, per, per, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
+        k_step<S, K, true, MODE_STEP, false, QF><<<dealt_grid, BLOCK, 0, a.stream>>>(
+            a.insts, a.tiles, a.ntiles, ch, ch, fs, gs, fd, gd, q, ph, rs, rd, nullptr);
     }
     return hipGetLastError();
 }

@@ -46,7 +46,7 @@ class lbm_options(C.Structure):
     _fields_ = [("storage", C.c_int32), ("kernel", C.c_int32), ("tile_rows", C.c_int32),
                 ("use_graph", C.c_int32), ("check_every", C.c_int32),
                 ("stores", C.c_int32), ("grid", C.c_int32), ("strip", C.c_int32),
-                ("narrow_tiles", C.c_int32)]
+                ("narrow_tiles", C.c_int32), ("deal", C.c_int32)]
 
 
 class lbm_diag(C.Structure):
@@ -92,7 +92,7 @@ def load():
     L.lbm_get_state.argtypes = [C.c_void_p, C.c_void_p, P(C.c_size_t)]
     L.lbm_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
     L.lbm_info.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_int32), P(C.c_int32),
-                           P(C.c_int32), P(C.c_int32), P(C.c_int32)]
+                           P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_int32)]
     L.lbm_last_error.argtypes = [C.c_void_p]
     L.lbm_last_error.restype = C.c_char_p
     L.lbm_destroy.argtypes = [C.c_void_p]
@@ -142,10 +142,11 @@ STORES = {"auto": 0, "cached": 1, "streaming": 2}
 GRID = {"auto": 0, "tiles": 1, "persistent": 2}
 STRIP = {"auto": 0, "rows": -1}
 NARROW = {"auto": 0, "off": -1, "on": 1}
+DEAL = {"auto": 0, "bands": -1}   # or a chunk of 1 to 4096 tiles
 
 
 def make_options(storage="f32", kernel="auto", tile_rows=0, use_graph=True, check_every=0,
-                 stores="auto", grid="auto", strip="auto", narrow="auto"):
+                 stores="auto", grid="auto", strip="auto", narrow="auto", deal="auto"):
     o = lbm_options()
     o.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     o.kernel = KERNEL[kernel] if isinstance(kernel, str) else int(kernel)
@@ -156,6 +157,7 @@ def make_options(storage="f32", kernel="auto", tile_rows=0, use_graph=True, chec
     o.grid = GRID[grid] if isinstance(grid, str) else int(grid)
     o.strip = STRIP[strip] if isinstance(strip, str) else int(strip)
     o.narrow_tiles = NARROW[narrow] if isinstance(narrow, str) else int(narrow)
+    o.deal = DEAL[deal] if isinstance(deal, str) else int(deal)
     return o
 
 
@@ -235,15 +237,16 @@ def lbm_set_state(ctx, blob: bytes):
 
 
 def lbm_info(ctx):
-    s, k, r, st, g, o, nw = (C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(),
-                             C.c_int32(), C.c_int32())
+    s, k, r, st, g, o, nw, d = (C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32(),
+                                C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32())
     _check(load().lbm_info(ctx, C.byref(s), C.byref(k), C.byref(r), C.byref(st), C.byref(g),
-                           C.byref(o), C.byref(nw)), ctx)
+                           C.byref(o), C.byref(nw), C.byref(d)), ctx)
     return {"step": s.value, "kernel": k.value, "tile_rows": r.value,
             "stores": {1: "cached", 2: "streaming"}.get(st.value, st.value),
             "grid": {1: "tiles", 2: "persistent"}.get(g.value, g.value),
             "strip": "rows" if o.value == -1 else o.value,
-            "narrow": {1: "on", -1: "off"}.get(nw.value, nw.value)}
+            "narrow": {1: "on", -1: "off"}.get(nw.value, nw.value),
+            "deal": "bands" if d.value == -1 else d.value}
 
 
 def lbm_last_error(ctx=None) -> str:
@@ -260,12 +263,12 @@ class Simulation:
 
     def __init__(self, case_or_cases, storage="f32", kernel="auto", tile_rows=0,
                  use_graph=True, check_every=0, stream=None, stores="auto", grid="auto",
-                 strip="auto", narrow="auto"):
+                 strip="auto", narrow="auto", deal="auto"):
         cs = case_or_cases if isinstance(case_or_cases, (list, tuple)) else [case_or_cases]
         self.cases = list(cs)
         params = [make_params(c) for c in self.cases]
         opts = make_options(storage, kernel, tile_rows, use_graph, check_every, stores, grid,
-                            strip, narrow)
+                            strip, narrow, deal)
         self.ctx = lbm_init(params, opts, [c["phi0"] for c in self.cases],
                             [c["ux0"] for c in self.cases], [c["uy0"] for c in self.cases],
                             stream=stream)

@@ -83,7 +83,8 @@ def test_invalid_boundary_and_options_rejected():
     assert e.value.code == lbm.LBM_ERR_PARAM and "periodic" in lbm.lbm_last_error()
     c = cases.static_drop(16, 16, R=4)
     for kw in ({"storage": 7}, {"tile_rows": 5}, {"kernel": 9}, {"check_every": -1},
-               {"stores": 3}, {"grid": 3}, {"grid": -1}, {"strip": 4}, {"strip": -2}):
+               {"stores": 3}, {"grid": 3}, {"grid": -1}, {"strip": 4}, {"strip": -2},
+               {"deal": -2}, {"deal": 4097}):
         with pytest.raises(lbm.LbmError) as e:
             _init(c, **kw)
         assert e.value.code == lbm.LBM_ERR_PARAM
@@ -107,7 +108,7 @@ def test_instance_beyond_4gib_rejected_before_device(storage, n):
 def test_null_context_calls():
     L = lbm.load()
     assert L.lbm_step(None, 1) == lbm.LBM_ERR_PARAM
-    assert L.lbm_info(None, None, None, None, None, None, None, None) == lbm.LBM_ERR_PARAM
+    assert L.lbm_info(None, None, None, None, None, None, None, None, None) == lbm.LBM_ERR_PARAM
     assert L.lbm_reduce(None, 0, None, None) == lbm.LBM_ERR_PARAM
     assert L.lbm_reduce_noalloc(None, 0, None, None) == lbm.LBM_ERR_PARAM
     L.lbm_destroy(None)

@@ -319,6 +319,32 @@ def test_narrow_tiles_bitwise_identical(storage, qf):
                                                                           k, key)
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_dealt_tiles_bitwise_identical(storage):
+    """The tiles of a batch of ragged grids (every boundary type; 117 tiles of 4 rows, 62 of
+    8) dealt to the XCDs in one band each, or in chunks of 1, 3 and 7 tiles, fused and split
+    kernels: the same bits.  The grid covers every tile once whatever the chunk, including a
+    last round of chunks that the tile list only partly fills."""
+    batch = _ragged_batch(seed=11)
+    ref = None
+    for rows in (4, 8):
+        for kernel in ("fused", "split"):
+            for deal in ("bands", 1, 3, 7):
+                with lbm.Simulation(batch, storage=storage, kernel=kernel, tile_rows=rows,
+                                    stores="cached", strip="rows", narrow="off",
+                                    deal=deal) as sim:
+                    assert sim.info()["deal"] == deal
+                    sim.step(21)
+                    out = [sim.moments(k) for k in range(len(batch))]
+                if ref is None:
+                    ref = out
+                    continue
+                for k in range(len(batch)):
+                    for key in ref[k]:
+                        assert np.array_equal(out[k][key], ref[k][key]), (rows, kernel, deal,
+                                                                          k, key)
+
+
 @pytest.mark.parametrize("law", [cases.NU_LINEAR, cases.NU_INVERSE, cases.MU_STEP])
 def test_viscosity_laws_f64(law):
     c = cases.random_state_case(40, 24, seed=5, visc_law=law)
@@ -715,14 +741,14 @@ def test_autotune_cache(tmp_path, monkeypatch):
     are ignored; results are the same bits either way.  The grid is 232 wide, so the choice
     includes the narrow tiles of its last 40 columns."""
     path = tmp_path / "tune.txt"
-    path.write_text("garbage line\nlbm-tune-v4 only-three-fields 1\n"
-                    "lbm-tune-v3 gfx950:s1 1 4 0 0 0\n")
+    path.write_text("garbage line\nlbm-tune-v5 only-three-fields 1\n"
+                    "lbm-tune-v4 gfx950:s1 1 4 0 0 0 0\n")
     monkeypatch.setenv("LBM_AUTOTUNE_CACHE", str(path))
     c = cases.droplet_impact(232, 96, D=40, Re=20)
 
     def recorded():
-        return [l for l in path.read_text().splitlines() if l.startswith("lbm-tune-v4 ") and
-                len(l.split()) == 8]
+        return [l for l in path.read_text().splitlines() if l.startswith("lbm-tune-v5 ") and
+                len(l.split()) == 9]
 
     with lbm.Simulation(c, storage="f32") as a:
         info_a = a.info()
@@ -730,18 +756,19 @@ def test_autotune_cache(tmp_path, monkeypatch):
         ref = a.moments()
     lines = recorded()
     assert len(lines) == 1
-    kern, rows, nt, pg, si, nw = (int(v) for v in lines[0].split()[2:])
+    kern, rows, nt, pg, si, nw, ch = (int(v) for v in lines[0].split()[2:])
     assert (kern, rows) == (info_a["kernel"], info_a["tile_rows"])
     assert (nt, pg) == (info_a["stores"] == "streaming", info_a["grid"] == "persistent")
     assert nw == (info_a["narrow"] == "on")
+    assert ch == (0 if info_a["deal"] == "bands" else info_a["deal"])
     with lbm.Simulation(c, storage="f32") as b:
         info_b = b.info()
         b.step(20)
         got = b.moments()
     assert recorded() == lines          # found in the cache: nothing appended
     assert (info_b["kernel"], info_b["tile_rows"], info_b["stores"], info_b["grid"],
-            info_b["strip"], info_b["narrow"]) == (info_a["kernel"], info_a["tile_rows"],
-                                                   info_a["stores"], info_a["grid"],
-                                                   info_a["strip"], info_a["narrow"])
+            info_b["strip"], info_b["narrow"], info_b["deal"]) == (
+                info_a["kernel"], info_a["tile_rows"], info_a["stores"], info_a["grid"],
+                info_a["strip"], info_a["narrow"], info_a["deal"])
     for k in ref:
         assert np.array_equal(ref[k], got[k])
