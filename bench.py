@@ -426,7 +426,8 @@ def main():
                     help="skip the host-to-host job timing (profiled runs: the step kernel's last "
                          "dispatches are then the timed ones)")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
+                    help="only run a plain 1 GiB device copy (calibrates HBM byte counters) "
+                         "and an elementwise streaming pass over the same bytes")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -438,14 +439,18 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
-        # a plain copy of known size: what the byte counters read for it calibrates them
+        # a plain copy of known size: what the byte counters read for it calibrates them;
+        # then the elementwise streaming pass of copy_bandwidth over the same bytes, whose
+        # traced duration is the device's streaming rate
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
         for _ in range(5):
             y.copy_(x)
+        for _ in range(5):
+            torch.neg(x, out=y)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4,
-                          "launches": 5}), flush=True)
+                          "launches": 5, "streaming_passes": 5}), flush=True)
         return
 
     from paper_1710_09541_amd import lbm
