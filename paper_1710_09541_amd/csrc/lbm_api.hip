@@ -369,24 +369,24 @@ uint64_t state_layout(const lbm_ctx* c) {
 void free_all(lbm_ctx* c) {
     for (int i = 0; i < 2; ++i) {
         for (int g = 0; g < NGRAPH; ++g) {
-            if (c->graph[g][i]) hipGraphExecDestroy(c->graph[g][i]);
+            if (c->graph[g][i]) (void)hipGraphExecDestroy(c->graph[g][i]);
             c->graph[g][i] = nullptr;
         }
-        if (c->f[i]) hipFree(c->f[i]);
-        if (c->g[i]) hipFree(c->g[i]);
+        if (c->f[i]) (void)hipFree(c->f[i]);
+        if (c->g[i]) (void)hipFree(c->g[i]);
         c->f[i] = c->g[i] = nullptr;
     }
     void* ptrs[] = {c->q,       c->q_tune,    c->phiplane, c->rplane[0], c->rplane[1],
                     c->d_insts, c->mom,       c->partials, c->red_out};
     for (void* p : ptrs)
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
     for (auto& by_rows : c->lists)
         for (auto& by_order : by_rows)
             for (auto& l : by_order)
-                if (l.dev) hipFree(l.dev);
-    if (c->h_red) hipHostFree(c->h_red);
-    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
-    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+                if (l.dev) (void)hipFree(l.dev);
+    if (c->h_red) (void)hipHostFree(c->h_red);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
 }
 
 // blocks per XCD of a persistent grid: as many as stay resident on the whole GPU (0 if
@@ -462,7 +462,7 @@ int launch_one(lbm_ctx* c, hipStream_t st) {
 void drop_graphs(lbm_ctx* c) {
     for (int g = 0; g < NGRAPH; ++g)
         for (int i = 0; i < 2; ++i) {
-            if (c->graph[g][i]) hipGraphExecDestroy(c->graph[g][i]);
+            if (c->graph[g][i]) (void)hipGraphExecDestroy(c->graph[g][i]);
             c->graph[g][i] = nullptr;
         }
 }
@@ -482,12 +482,12 @@ int capture_steps(lbm_ctx* c, int g, int from) {
     c->cur = save_cur;
     c->streamed = save_streamed;
     if (rc != LBM_OK) {
-        if (gr) hipGraphDestroy(gr);
+        if (gr) (void)hipGraphDestroy(gr);
         return rc;
     }
     if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
     e = hipGraphInstantiate(&c->graph[g][from], gr, nullptr, nullptr, 0);
-    hipGraphDestroy(gr);
+    (void)hipGraphDestroy(gr);
     if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
     return LBM_OK;
 }
@@ -737,7 +737,7 @@ int autotune(lbm_ctx* c) {
         if (e == hipSuccess) e = hipEventCreate(&e0);
         if (e == hipSuccess) e = hipEventCreate(&e1);
         if (e != hipSuccess) {
-            if (e0) hipEventDestroy(e0);
+            if (e0) (void)hipEventDestroy(e0);
             free_temps();
             return hip_fail(c, e, "autotune set-up");
         }
@@ -777,22 +777,28 @@ int autotune(lbm_ctx* c) {
         for (int ci = 0; ci < nc && rc == LBM_OK; ++ci) {
             StepArgs a, b;
             args_of(cands[ci], a, b);
-            hipEventRecord(e0, c->stream);
+            hipError_t e = hipEventRecord(e0, c->stream);
+            if (e != hipSuccess) {
+                rc = hip_fail(c, e, "autotune event");
+                break;
+            }
             for (int k = 0; k < reps; ++k) {
-                hipError_t e = launch_step(c->storage, (k & 1) ? b : a);
+                e = launch_step(c->storage, (k & 1) ? b : a);
                 if (e != hipSuccess) {
                     rc = hip_fail(c, e, "autotune launch");
                     break;
                 }
             }
             if (rc != LBM_OK) break;
-            hipEventRecord(e1, c->stream);
-            hipError_t e = hipEventSynchronize(e1);
+            e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            // a time that could not be read must not make its candidate look fastest
+            if (e == hipSuccess && round >= 0)
+                e = hipEventElapsedTime(&t[(size_t)ci * NREP + round], e0, e1);
             if (e != hipSuccess) {
-                rc = hip_fail(c, e, "autotune synchronize");
+                rc = hip_fail(c, e, "autotune timing");
                 break;
             }
-            if (round >= 0) hipEventElapsedTime(&t[(size_t)ci * NREP + round], e0, e1);
         }
     }
     if (rc == LBM_OK) {
@@ -815,8 +821,8 @@ int autotune(lbm_ctx* c) {
             }
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     free_temps();
     return rc;
 }
@@ -964,13 +970,15 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
     e = hipHostMalloc((void**)&c->h_red, 16 * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) return bail(hip_fail(c, e, "hipHostMalloc"));
     // padding between and inside planes is never read, but keep it defined
-    for (int i = 0; i < 2; ++i) {
-        hipMemsetAsync(c->f[i], 0, dist_bytes, c->stream);
-        hipMemsetAsync(c->g[i], 0, dist_bytes, c->stream);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipMemsetAsync(c->f[i], 0, dist_bytes, c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(c->g[i], 0, dist_bytes, c->stream);
     }
-    zero_n_async(c->phiplane, c->phi_elems * c->qsize, c->stream);
-    zero_n_async(c->q, c->q_elems * sizeof(double), c->stream);
-    for (int i = 0; i < 2; ++i) zero_n_async(c->rplane[i], c->mp_elems * sizeof(float), c->stream);
+    if (e == hipSuccess) e = zero_n_async(c->phiplane, c->phi_elems * c->qsize, c->stream);
+    if (e == hipSuccess) e = zero_n_async(c->q, c->q_elems * sizeof(double), c->stream);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i)
+        e = zero_n_async(c->rplane[i], c->mp_elems * sizeof(float), c->stream);
+    if (e != hipSuccess) return bail(hip_fail(c, e, "clearing the state buffers"));
 
     std::vector<InstDev> hd(n_inst);
     for (int k = 0; k < n_inst; ++k) hd[k] = c->inst[k].d;
@@ -1014,11 +1022,11 @@ int lbm_init(const lbm_params* p, int32_t n_inst, const lbm_options* opt,
                             c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) {
-            hipFree(stage);
+            (void)hipFree(stage);
             return bail(hip_fail(c, e, "initial state"));
         }
     }
-    hipFree(stage);
+    (void)hipFree(stage);
     c->cur = 0;
     c->streamed = true;
     c->step = 0;
@@ -1279,7 +1287,7 @@ const char* lbm_last_error(const lbm_ctx* c) {
 
 void lbm_destroy(lbm_ctx* c) {
     if (!c) return;
-    if (c->stream) hipStreamSynchronize(c->stream);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);   // nothing to report to
     free_all(c);
     delete c;
 }
