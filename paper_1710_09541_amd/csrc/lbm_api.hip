@@ -30,7 +30,7 @@ namespace {
 thread_local std::string g_thread_err;
 
 constexpr uint64_t STATE_MAGIC = 0x4c424d5046534154ull;  // "LBMPFSAT"
-constexpr int STATE_VERSION = 6;
+constexpr int STATE_VERSION = 7;
 // steps per captured graph, shortest first: each graph launch costs a few microseconds
 // between the last kernel of one graph and the first of the next, which long graphs spread
 // over more steps (measured: 64 steps per graph 0.6 % faster than 16 at 1024^2 FP32 and 4 %
@@ -43,13 +43,13 @@ constexpr int NGRAPH = 3;
 constexpr int NSTRIP = 3;
 constexpr int STRIP_TILES[NSTRIP] = {0, 8, 16};
 constexpr int GRAPH_STEPS[NGRAPH] = {2, 16, 64};
-constexpr int PLANE_PAD = 192;
+constexpr int PLANE_PAD = 192;  // elements added to each plane: breaks power-of-two plane strides
 // tiles per chunk when the tiles are dealt to the XCDs in chunks: the longest accepted, and
 // the one the autotuner times against one band per XCD (measured on a batch of 256 ragged
 // instances, FP32: chunks of 4, 8, 16 and 64 tiles +8.5, +9.6, +10.2 and +7.6 % over bands;
 // on single grids of 1024^2 and 4096^2 bands win by 4 to 12 %)
 constexpr int MAX_CHUNK = 4096;
-constexpr int AUTO_CHUNK = 16;  // elements added to each plane: breaks power-of-two plane strides
+constexpr int AUTO_CHUNK = 16;
 
 // Device scratch of lbm_reduce_noalloc, for callers that cannot allocate: the five FP64
 // moment planes of one instance of at most NOALLOC_MAX_NODES nodes, then the reduction's
@@ -97,7 +97,7 @@ struct lbm_ctx {
     int storage = STORE_F32;
     size_t esize = 4;          // bytes per stored distribution value
     size_t qsize = 4;          // bytes per split-kernel phi value (compute type)
-    int64_t dist_elems = 0;    // elements of one distribution set (all instances, 9 planes)
+    int64_t dist_elems = 0;    // elements of one distribution set (all instances, 9 populations)
     int64_t q_elems = 0;       // FP64 phi u: a double2 per node and instance
     int64_t phi_elems = 0;     // split-kernel phi: 1 plane per instance
     int64_t mp_elems = 0;      // per-node state, in floats: 16-bit format, a float4 per node;

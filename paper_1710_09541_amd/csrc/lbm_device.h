@@ -20,7 +20,8 @@ constexpr int REDUCE_MAX_BLOCKS = 1024; // blocks of the partial pass at most
 // Per-instance constants, read with uniform (scalar) loads.  Distances are in elements.
 struct InstDev {
     int32_t nx, ny, pitch, bc_lo, bc_hi, visc_law, grad_scheme;
-    int64_t off_dist;   // offset of this instance's plane 0 in the f and g arrays
+    int64_t off_dist;   // offset of this instance's distributions in the f and g arrays:
+                        // 9 * plane elements, [y][i][x] (FP64, FP32) or [i][y][x] (16-bit)
     int64_t off_q;      // FP64 format: offset of its two (phi u) planes in the q array
     int64_t off_phi;    // offset of its phi plane (split kernel)
     int64_t off_mp;     // offset (in floats) of its per-node state: 16-bit format, a float4
