@@ -137,9 +137,9 @@ enum {
 
 /* Per-instance problem parameters. */
 typedef struct {
-    int32_t nx, ny;           /* lattice size, each >= 3; one instance's 9 population planes
-                                 must stay below 4 GiB in the chosen storage (FP64: about
-                                 7700 x 7700 nodes) */
+    int32_t nx, ny;           /* lattice size, each >= 3; one instance's 9 populations of a
+                                 lattice (9 x ny x nx rounded up to 64) must stay below 4 GiB
+                                 in the chosen storage (FP64: about 7700 x 7700 nodes) */
     int32_t bc_ylo, bc_yhi;   /* LBM_BC_*; PERIODIC must be set on both sides or on neither */
     int32_t visc_law;         /* LBM_VISC_* */
     int32_t grad_scheme;      /* LBM_GRAD_* */
