@@ -56,6 +56,8 @@ def test_committed_profiles_name_their_commands_and_kernel():
         if name.startswith("step_"):
             text = open(path).read()
             assert "rocprofv3" in text and "Kernel code hash" in text, name
+            # the device's streaming rate beside the copy that calibrates the counters
+            assert "Streaming rate:" in text and "Copy calibration:" in text, name
             # the summary averages the step kernel's last `steps` dispatches, which are the
             # timed ones only when the traced bench command skips the host round trip
             traced = [l for l in text.splitlines() if "--kernel-trace" in l and "bench.py" in l

@@ -36,6 +36,11 @@ def test_bench_line_contract():
     assert abs(rf["achieved"] / (rf["alg_bytes_per_launch"] / (d["ms_per_step"] * 1e-3) / 1e9) - 1) < 1e-3
     assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-3
     assert 0 < rf["frac"] < 1 and 0 < rf["frac_of_copy"] < 1.5
+    # the device's streaming rate, measured in the same run
+    assert rf["copy_gbs"] > 0 and abs(rf["frac_of_copy"] - rf["achieved"] / rf["copy_gbs"]) < 1e-3
+    # the launch configuration the autotuner chose, XCD dealing included
+    deal = d["config"]["deal"]
+    assert deal == "bands" or 1 <= deal <= 4096
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["value_1_thread"] > 0
     assert cb["cores"] >= 1 and cb["cores_1_thread"] == 1
