@@ -198,7 +198,7 @@ constexpr int state_floats() {
 // population stride `plane`, row stride `pitch`.  Interleaved rows: [y][i][pitch],
 // population stride `pitch`, row stride 9 pitch, so a tile's 9 rows of a lattice lie
 // together in memory and a step runs fewer concurrent streams.  Measured: FP32 +0.7 to
-// +1.5 %, FP64 +8.3 % at 4096^2 (-1 % on a batch), 16-bit storage -0.5 to -1.7 %; each
+// +1.5 %, FP64 +8.3 % at 4096^2 (-1 % on a batch), 16-bit storage -0.9 to -3.1 %; each
 // format takes the faster one.
 template <typename S>
 constexpr bool rows_interleaved() {
