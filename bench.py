@@ -142,14 +142,14 @@ def traffic_from_profile(wl, storage):
 
 
 def time_gpu(cs, storage, steps, warmup, kernel, tile_rows, final_stats=False, stores="auto",
-             grid="auto"):
+             grid="auto", deal="auto"):
     """Milliseconds of `steps` steps after `warmup` untimed ones.  With final_stats, also
     the first instance's L and sum(phi) drift at the end (read after the timed region)."""
     import torch
     from paper_1710_09541_amd import lbm
     stream = torch.cuda.Stream()
     sim = lbm.Simulation(cs, storage=storage, kernel=kernel, tile_rows=tile_rows,
-                         stream=stream.cuda_stream, stores=stores, grid=grid)
+                         stream=stream.cuda_stream, stores=stores, grid=grid, deal=deal)
     info = sim.info()
     s0 = sim.reduce()["sum_phi"] if final_stats else None
     sim.step(warmup)
@@ -171,11 +171,11 @@ def time_gpu(cs, storage, steps, warmup, kernel, tile_rows, final_stats=False, s
 
 
 def measure(cs, storage, steps, warmup, kernel="auto", tile_rows=0, final_stats=False,
-            stores="auto", grid="auto"):
+            stores="auto", grid="auto", deal="auto"):
     nodes = sum(c["nx"] * c["ny"] for c in cs)
     qf = cs[0].get("f_lattice", 9)
     ms, info, stats = time_gpu(cs, storage, steps, warmup, kernel, tile_rows, final_stats, stores,
-                               grid)
+                               grid, deal)
     per_launch_s = ms / 1e3 / steps
     ach = alg_bytes(storage, qf) * nodes / per_launch_s / 1e9
     return {"mlups": nodes * steps / (ms / 1e3) / 1e6, "ms_per_step": ms / steps,
@@ -412,6 +412,14 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--stores", default="auto", choices=["auto", "cached", "streaming"])
     ap.add_argument("--grid", default="auto", choices=["auto", "tiles", "persistent"])
+    def deal_arg(v):
+        if v in ("auto", "bands"):
+            return v
+        if v.isdigit() and 1 <= int(v) <= 4096:
+            return int(v)
+        raise argparse.ArgumentTypeError("auto, bands or a chunk of 1 to 4096 tiles")
+    ap.add_argument("--deal", default="auto", type=deal_arg,
+                    help="tiles to the XCDs: auto, bands, or a chunk of 1 to 4096 tiles")
     ap.add_argument("--variants", default=None,
                     help="other storages to time, comma-separated ('none' for none; default "
                          "f64 for the batch, f64,f16 otherwise)")
@@ -429,6 +437,7 @@ def main():
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters) "
                          "and an elementwise streaming pass over the same bytes")
     args = ap.parse_args()
+    deal = args.deal
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this implementation has no multi-GPU path "
@@ -482,7 +491,7 @@ def main():
     others = [] if variants in ("", "none") else variants.split(",")
     for st in [args.storage] + [v for v in others if v and v != args.storage]:
         r = measure(cs, st, args.steps, args.warmup, args.kernel, args.tile_rows,
-                    final_stats=single, stores=args.stores, grid=args.grid)
+                    final_stats=single, stores=args.stores, grid=args.grid, deal=deal)
         log("%s: %.1f MLUPS, %.4f ms/step, %.0f GB/s algorithmic (%d rows, %s stores, %s grid, "
             "tile order: %s, deal: %s)" % (st, r["mlups"], r["ms_per_step"], r["achieved_gbs"],
                                           r["tile_rows"], r["stores"], r["grid"], r["tile_order"],
